@@ -1,0 +1,101 @@
+"""Input generators: sparsity structure pinned to the sizes the paper prints."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2109_01232_amd import problems as P
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("case", _load("paper_stencil_sizes.json")["cases"], ids=lambda c: c["name"])
+def test_stencil_counts_match_paper(case):
+    """Eliminated-Dirichlet stencils reproduce the paper's N / nnz exactly."""
+    n = case["n"]
+    if case["dim"] == 2:
+        assert n * n == case["N"]
+        assert P.stencil_nnz_2d5(n) == case["nnz"]
+    else:
+        assert n ** 3 == case["N"]
+        assert P.stencil_nnz_3d7(n) == case["nnz"]
+
+
+@pytest.mark.slow
+def test_generator_builds_paper_sizes():
+    """The generator itself (not only the closed form) hits the printed counts."""
+    A = P.conv_diff(2, 1500, 10.0, (1.0, 1.0))
+    assert (A.n, A.nnz) == (2250000, 11244000)
+    A = P.conv_diff(3, 150, 10.0, (1.0, 1.0, 1.0), (1.0, 1.0, 1e-2))
+    assert (A.n, A.nnz) == (3375000, 23490000)
+
+
+@pytest.mark.parametrize("n", [3, 4, 7, 13])
+def test_small_stencils_structure(n):
+    A2 = P.conv_diff(2, n, 10.0, (1.0, 1.0))
+    assert A2.nnz == P.stencil_nnz_2d5(n)
+    A3 = P.conv_diff(3, n, 10.0, (1.0, 1.0, 1.0))
+    assert A3.nnz == P.stencil_nnz_3d7(n)
+    A27 = P.varcoef27(n, 5)
+    assert A27.nnz == P.stencil_nnz_27(n)
+    for A in (A2, A3, A27):
+        rp = A.rowptr
+        assert rp[0] == 0 and np.all(np.diff(rp) > 0)
+        for i in range(A.n):
+            cols = A.colidx[rp[i]:rp[i + 1]]
+            assert np.all(np.diff(cols) > 0), "columns ascending within a row"
+            assert i in cols, "diagonal present"
+
+
+def test_convdiff_stencil_values():
+    """Interior row of the 2D operator: centre 2(k1+k2), neighbours -k_d -/+ Pe w_d h / 2."""
+    n, Pe, w, k = 9, 30.0, (0.6, -0.8), (1.0, 0.25)
+    A = P.conv_diff(2, n, Pe, w, k).scipy().toarray()
+    h = 1.0 / (n + 1)
+    i = 4 + n * 4
+    assert A[i, i] == pytest.approx(2 * (k[0] + k[1]))
+    assert A[i, i - 1] == pytest.approx(-k[0] - Pe * w[0] * h / 2)
+    assert A[i, i + 1] == pytest.approx(-k[0] + Pe * w[0] * h / 2)
+    assert A[i, i - n] == pytest.approx(-k[1] - Pe * w[1] * h / 2)
+    assert A[i, i + n] == pytest.approx(-k[1] + Pe * w[1] * h / 2)
+    # Pe = 0 gives the symmetric (scaled) Laplacian
+    L = P.conv_diff(2, n, 0.0, (1.0, 1.0)).scipy()
+    assert abs(L - L.T).max() == 0.0
+
+
+def test_varcoef27_is_m_matrix_with_row_sum():
+    A = P.varcoef27(6, 11)
+    S = A.scipy()
+    rs = S @ np.ones(A.n)
+    assert np.max(np.abs(rs - 0.05)) <= 1e-13
+    D = S.diagonal()
+    off = S - __import__("scipy.sparse", fromlist=["diags"]).diags(D)
+    assert off.max() < 0 or off.nnz == 0 or off.data.max() < 0
+    assert np.all(D > np.asarray(abs(off).sum(axis=1)).ravel())
+    assert abs(S - S.T).max() > 0.1, "nonsymmetric"
+    # entries within the documented range: -(1 +- 0.3) +- 0.5
+    assert off.data.min() >= -1.8 - 1e-12 and off.data.max() <= -0.2 + 1e-12
+
+
+def test_seeded_reproducible():
+    a = P.convdiff2d_system(3, n=30)
+    b = P.convdiff2d_system(3, n=30)
+    c = P.convdiff2d_system(4, n=30)
+    assert np.array_equal(a.b, b.b) and a.meta["Pe"] == b.meta["Pe"]
+    assert not np.array_equal(a.b, c.b)
+    assert 1.0 <= a.meta["Pe"] <= 100.0
+    s1, s2 = P.chooser_system(7, n_max=5e4), P.chooser_system(7, n_max=5e4)
+    assert np.array_equal(s1.A.vals, s2.A.vals) and np.array_equal(s1.b, s2.b)
+
+
+def test_rhs_is_A_u():
+    s = P.parity_system()
+    assert np.allclose(s.A.scipy() @ np.ones(s.A.n), s.b)
+    # b = A * ones is nonzero only next to the boundary (interior rows sum to 0 when Pe terms cancel)
+    assert s.A.n == 4096 and s.A.nnz == 20224
