@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Time-to-1e-10 of GMRES-IR (fp32 inner GMRES(50), fp64 refinement) on one MI355X.
+
+Workload: 2D convection-diffusion, 5-point centred differences on a
+1000 x 1000 grid (N = 1e6, 4,996,000 nonzeros), Peclet number drawn from
+U[1, 100] with seed 0, wind (1, 1), b = A u with u ~ U[-1, 1], x0 = 0,
+relative residual tolerance 1e-10.  One step = one complete solve (fp64
+residual, cast, inner cycles of SpMV + CGS2 + Givens, fp64 correction, until
+||b - A x|| / ||b|| <= 1e-10).  fp64 GMRES(50) on the same GPU and system is
+timed beside it.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (see the keys below).  Options for profiling runs:
+--no-cpu-baseline, --no-fp64, --no-profile, --copy-calibration (a plain
+device copy of known size, for scaling the HBM traffic counters).
+"""
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time-to-1e-10 residual (s), GMRES-IR FP32/BF16 vs FP64 GMRES; SpMV+CGS2 HBM GB/s"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(system, gpu_iters, budget_s=20.0):
+    """The CPU oracle on a bounded sample of the same solve, extrapolated per iteration."""
+    import numpy as np
+
+    from oracle import linalg as L
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    iters = 0
+    t0 = time.perf_counter()
+    sample_iters = 100
+    while True:
+        r = L.gmres_ir(system.A, system.b, m=50, rtol=1e-10, inner="fp32", max_iters=sample_iters, check_mode=1)
+        iters = r.iters
+        el = time.perf_counter() - t0
+        if el > 5.0 or sample_iters >= 400:
+            break
+        sample_iters *= 2
+        t0 = time.perf_counter()
+    per_iter = el / max(iters, 1)
+    return {
+        "value": per_iter * gpu_iters,
+        "unit": "s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"{iters} inner iterations ({iters // 50} restart cycles) of the oracle's GMRES-IR(50) fp32 on "
+                  f"the same 1000x1000 system in {el:.1f} s, extrapolated to the GPU run's {gpu_iters} iterations",
+        "per_iter_s": per_iter,
+        "cpu": platform.processor() or platform.machine(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--n", type=int, default=1000)
+    ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--basis", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU decomposition is a design in DESIGN.md, not built)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2109_01232_amd import binding as B
+    from paper_2109_01232_amd import problems as P
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    B.lib()
+
+    if args.copy_calibration:
+        # plain copy of a known size (256 MiB read + 256 MiB written) for the counter scaling
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 5}), flush=True)
+        return
+
+    log("building system")
+    system = P.convdiff2d_system(args.seed, n=args.n)
+    A = system.A
+    M = B.Matrix.from_csr(A)
+    b = torch.from_numpy(system.b).cuda()
+    x = torch.zeros_like(b)
+    ws = B.Workspace()
+    p_ir = B.make_params(restart=args.restart, inner="fp32", basis=args.basis, rtol=1e-10, check_mode=1)
+    p_64 = B.make_params(restart=args.restart, inner="fp64", rtol=1e-10, check_mode=1)
+
+    def run(p):
+        x.zero_()
+        st, d, _ = B.gmresir_solve(M, b, x, p, ws=ws)
+        return d
+
+    for _ in range(args.warmup):
+        run(p_ir)
+    torch.cuda.synchronize()
+    log("timed GMRES-IR steps", args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        d_ir = run(p_ir)
+    torch.cuda.synchronize()
+    t_ir = (time.perf_counter() - t0) / args.steps
+    xs = x.cpu().numpy()
+    sol_err = float(np.linalg.norm(xs - system.u) / np.linalg.norm(system.u))
+    true_resid = float(np.linalg.norm(system.b - A.scipy() @ xs) / np.linalg.norm(system.b))
+    log(f"IR: {t_ir:.4f} s/solve iters={d_ir['iters']} resid={true_resid:.3e}")
+
+    out = {
+        "metric": METRIC,
+        "value": t_ir,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_ir * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"convdiff2d_{args.n}x{args.n}_5pt_seed{args.seed}",
+            "N": A.n, "nnz": A.nnz, "Pe": system.meta["Pe"], "restart": args.restart,
+            "rtol": 1e-10, "inner": "fp32", "basis": args.basis, "check_mode": 1,
+        },
+        "iters": d_ir["iters"],
+        "refinements": d_ir["refinements"],
+        "rel_resid_true": true_resid,
+        "sol_err_vs_u": sol_err,
+    }
+
+    if not args.no_fp64:
+        run(p_64)
+        torch.cuda.synchronize()
+        steps64 = max(1, min(args.steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(steps64):
+            d_64 = run(p_64)
+        torch.cuda.synchronize()
+        t_64 = (time.perf_counter() - t0) / steps64
+        log(f"FP64: {t_64:.4f} s/solve iters={d_64['iters']}")
+        out["fp64_gmres_s"] = t_64
+        out["fp64_iters"] = d_64["iters"]
+        out["fp64_rel_resid_true"] = d_64["rel_resid_true"]
+        out["speedup_vs_fp64"] = t_64 / t_ir
+
+    if not args.no_profile:
+        # one more solve with HIP events around every kernel (on the solve's stream)
+        p_prof = B.make_params(restart=args.restart, inner="fp32", basis=args.basis, rtol=1e-10, check_mode=1,
+                               profile=1)
+        d_prof = run(p_prof)
+        cats = ("spmv_proj", "update_proj", "update_norm")
+        dom = max(cats, key=lambda c: d_prof["cat_time_s"][c])
+        tt, bb, nl = d_prof["cat_time_s"][dom], d_prof["cat_bytes"][dom], d_prof["cat_launches"][dom]
+        achieved = bb / tt / 1e9 if tt > 0 else 0.0
+        out["roofline"] = {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+            "avg_launch_us": tt / max(nl, 1) * 1e6, "avg_bytes_per_launch": bb / max(nl, 1),
+        }
+        out["breakdown_ir"] = {
+            c: {"s": d_prof["cat_time_s"][c], "GBps": (d_prof["cat_bytes"][c] / d_prof["cat_time_s"][c] / 1e9
+                                                      if d_prof["cat_time_s"][c] > 0 else 0.0),
+                "launches": d_prof["cat_launches"][c]}
+            for c in B.CATEGORIES if d_prof["cat_launches"][c] > 0
+        }
+        if not args.no_fp64:
+            d64p = run(B.make_params(restart=args.restart, inner="fp64", rtol=1e-10, check_mode=1, profile=1))
+            out["breakdown_fp64"] = {
+                c: {"s": d64p["cat_time_s"][c], "GBps": (d64p["cat_bytes"][c] / d64p["cat_time_s"][c] / 1e9
+                                                        if d64p["cat_time_s"][c] > 0 else 0.0),
+                    "launches": d64p["cat_launches"][c]}
+                for c in B.CATEGORIES if d64p["cat_launches"][c] > 0
+            }
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(system, d_ir["iters"])
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+// Device-side building blocks of libgmresir for gfx950 (wave64, 256 CUs in
+// 8 XCDs): basis storage types, wave/block reductions, the deterministic
+// grid-wide "last block" reduction, and the shared device state of a cycle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace gir {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+constexpr int NWAVES = BLOCK / WAVE;
+
+typedef uint16_t bf16_t;
+
+// ---------------------------------------------------------------------------
+// basis storage: S is the stored element type, T the arithmetic type
+// ---------------------------------------------------------------------------
+
+template <typename S, typename T>
+struct Basis;
+
+template <>
+struct Basis<double, double> {
+  static __device__ __forceinline__ double load(const double* p) { return *p; }
+  static __device__ __forceinline__ double round(double v) { return v; }
+  static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
+};
+
+template <>
+struct Basis<float, float> {
+  static __device__ __forceinline__ float load(const float* p) { return *p; }
+  static __device__ __forceinline__ float round(float v) { return v; }
+  static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+};
+
+// bfloat16: the top half of the binary32 pattern, rounded to nearest even.
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x0040u);  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <>
+struct Basis<bf16_t, float> {
+  static __device__ __forceinline__ float load(const bf16_t* p) { return bf16_bits_to_f32(*p); }
+  static __device__ __forceinline__ float round(float v) { return bf16_bits_to_f32(f32_to_bf16_bits(v)); }
+  static __device__ __forceinline__ void store(bf16_t* p, float v) { *p = f32_to_bf16_bits(v); }
+};
+
+// Load element (row, column c) of a column-major basis: the column base is
+// wave-uniform (scalar registers) and the row offset is a 32-bit byte offset
+// shared by all columns, so each load costs no per-column vector address.
+template <typename S, typename T>
+__device__ __forceinline__ T vload(const S* V, long ldv, int c, uint32_t roff) {
+  const char* base = (const char*)V + (size_t)c * (size_t)ldv * sizeof(S);
+  return Basis<S, T>::load((const S*)(base + roff));
+}
+
+template <typename T>
+struct Unit;
+template <>
+struct Unit<float> {
+  static constexpr double roundoff = 5.9604644775390625e-08;  // 2^-24
+};
+template <>
+struct Unit<double> {
+  static constexpr double roundoff = 1.1102230246251565e-16;  // 2^-53
+};
+
+// ---------------------------------------------------------------------------
+// device state of one solve (lives in the caller's workspace)
+// ---------------------------------------------------------------------------
+
+enum : int32_t { F_DONE = 1, F_BREAKDOWN = 2, F_NUMERIC = 4, F_STOPPED = 8 };
+
+struct StateHdr {
+  double beta;      // ||b||_2 (fp64)
+  double gamma;     // ||r||_2 of the current outer residual (fp64)
+  double gamma_in;  // norm of the current cycle's right-hand side (inner precision)
+  double inv_h;     // 1 / norm of the vector held in wtmp: next basis vector = wtmp * inv_h
+  double stop_abs;  // implicit early exit when |g_{j+1}| <= stop_abs (< 0: off)
+  double rtol;
+  double implicit;  // |g_{k}| of the last step (implicit residual, cycle units)
+  int32_t check_mode;
+  int32_t k;            // Arnoldi steps completed in the current cycle
+  int32_t flags;        // F_* of the current cycle
+  int32_t cycle_k;      // k and flags of the last finished cycle (kept across
+  int32_t cycle_flags;  // the reset a new cycle start does)
+  int32_t pad[3];
+  uint32_t counter[8];  // tickets of the grid-wide reductions (reset by the last block)
+};
+
+struct State {
+  StateHdr* hdr;
+  double* h1;    // m+1   first-pass projection coefficients
+  double* h2;    // m+1   second-pass projection coefficients
+  double* Hbar;  // (m+1) x m unrotated Hessenberg matrix, column-major, ld
+  double* R;     // (m+1) x m rotated (triangular) columns
+  double* cs;    // m     Givens cosines
+  double* sn;    // m     Givens sines
+  double* g;     // m+1   rotated right-hand side
+  double* y;     // m     least-squares solution of the finished cycle
+  double* hist;  // m     |g_{j+1}| / gamma_in per step
+  int ld;        // m+1
+};
+
+// CSR operand of the SpMV kernels; vals has element type MT.
+struct Csr {
+  int n;
+  int ntiles;
+  const int* rowptr;
+  const int* col;
+  const void* vals;
+  const int* tile_row;  // ntiles+1 row boundaries
+};
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+// Hardware block b runs on XCD (b mod 8); map it to a logical block so that
+// each XCD owns a contiguous eighth of the rows (its L2 then holds the x
+// neighbourhood the SpMV gathers from).
+__device__ __forceinline__ int logical_block() {
+  const int b = blockIdx.x, B = gridDim.x;
+  return (B % 8 == 0) ? (b % 8) * (B / 8) + b / 8 : b;
+}
+
+// Row range [r0, r1) of this block for row-parallel kernels.
+__device__ __forceinline__ void block_rows(int n, int& r0, int& r1) {
+  const int B = gridDim.x;
+  long chunk = ((long)n + B - 1) / B;
+  chunk = (chunk + 63) & ~63L;
+  long a = (long)logical_block() * chunk;
+  r0 = (int)(a < n ? a : n);
+  long e = a + chunk;
+  r1 = (int)(e < n ? e : n);
+}
+
+// Reduce acc[0..nv) over the block (fixed order: butterfly in each wave, then
+// waves in order).  Result in out[0..nv) (LDS), visible to all threads.
+template <typename T, int NV>
+__device__ __forceinline__ void block_reduce_vec(const T (&acc)[NV], int nv, T* lds, T* out) {
+  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    if (c < nv) {
+      T v = wave_sum(acc[c]);
+      if (lane == 0) lds[wid * NV + c] = v;
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < nv; c += BLOCK) {
+    T s = lds[c];
+#pragma unroll
+    for (int w = 1; w < NWAVES; ++w) s += lds[w * NV + c];
+    out[c] = s;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* lds /* NWAVES */) {
+  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  T s = lds[0];
+#pragma unroll
+  for (int w = 1; w < NWAVES; ++w) s += lds[w];
+  __syncthreads();
+  return s;
+}
+
+// Cross-block reductions are two kernels: the producer grid stores one
+// partial vector per block (column-major, part[c * MAX_BLOCKS + block]) and a
+// one-block tail kernel sums them in a fixed order after the kernel boundary
+// has published them.  (A "last block" ticket inside the producer would need
+// a device-scope release per block, which on gfx950 writes back the whole L2
+// of the XCD every time.)
+constexpr int MAX_BLOCKS = 1024;
+constexpr int RED_BATCH = 4;                   // columns reduced per wave and batch
+constexpr int RED_LOADS = MAX_BLOCKS / WAVE;   // partials per lane and column
+
+template <typename T>
+__device__ __forceinline__ void store_partials(const T* vals, int nv, T* part) {
+  for (int c = threadIdx.x; c < nv; c += BLOCK) part[(size_t)c * MAX_BLOCKS + blockIdx.x] = vals[c];
+}
+
+// out[c] = sum over the B producer blocks of part[c][b], one wave per column:
+// lane l sums b = l + 64 i in order of i, then the lanes by a fixed butterfly.
+// All loads of a batch are issued before any add.  out is LDS; ends with a
+// barrier.
+template <typename T>
+__device__ __forceinline__ void reduce_partials(const T* part, int nv, int B, T* out) {
+  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+  const int nwaves = blockDim.x / WAVE;
+  for (int c0 = wid * RED_BATCH; c0 < nv; c0 += nwaves * RED_BATCH) {
+    T s[RED_BATCH];
+#pragma unroll
+    for (int q = 0; q < RED_BATCH; ++q) s[q] = T(0);
+    // branch-free: out-of-range blocks read a valid address and add 0
+#pragma unroll
+    for (int i = 0; i < RED_LOADS; ++i) {
+      const int b = lane + WAVE * i;
+      const int bc = b < B ? b : B - 1;
+#pragma unroll
+      for (int q = 0; q < RED_BATCH; ++q) {
+        const int c = (c0 + q < nv) ? c0 + q : nv - 1;
+        const T v = part[(size_t)c * MAX_BLOCKS + bc];
+        s[q] += (b < B) ? v : T(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RED_BATCH; ++q) {
+      const T t = wave_sum(s[q]);
+      if (lane == 0 && c0 + q < nv) out[c0 + q] = t;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace gir

@@ -1,0 +1,1185 @@
+// C-ABI entry points and host driver of libgmresir (see include/gmresir.h).
+//
+// The driver owns no device memory: every buffer is carved out of the
+// caller's workspace.  One refinement step of GMRES-IR (Algorithm 2) is
+// enqueued without host synchronisation -- m iterations of three kernels,
+// the back substitution, the fp64 correction and the fp64 residual -- and
+// the host reads the small state header once per refinement to decide on
+// convergence (the paper's restart-time check).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "gmresir.h"
+#include "kernels.hpp"
+
+using namespace gir;
+
+struct gmresir_matrix {
+  int64_t n, nnz;
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const double* vals64;
+  float* vals32;
+  int32_t* tile_row;
+  int ntiles;
+  int device;
+};
+
+namespace {
+
+constexpr int MAX_GRID = 1024;  // <= MAX_BLOCKS (partials per reduction)
+constexpr int PSTRIDE = 136;  // >= 129 partial values per block
+constexpr size_t ALIGN = 256;
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return GMRESIR_ERR_HIP;                                                      \
+    }                                                                              \
+  } while (0)
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// ---------------------------------------------------------------------------
+// launch configuration: blocks = CUs x resident blocks per CU (one wave of
+// blocks), capped by the useful parallelism
+// ---------------------------------------------------------------------------
+
+int device_cus(int dev) {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  cache[dev] = cus;
+  return cus;
+}
+
+int resident_grid(const void* kern, size_t smem) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find({dev, kern});
+    if (it != cache.end()) return it->second;
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, BLOCK, smem) != hipSuccess || nb <= 0) nb = 1;
+  int g = std::min(MAX_GRID, device_cus(dev) * nb);
+  std::lock_guard<std::mutex> lk(mu);
+  cache[{dev, kern}] = g;
+  return g;
+}
+
+int grid_rows(const void* kern, int64_t n) {
+  int g = resident_grid(kern, 0);
+  int64_t want = (n + BLOCK - 1) / BLOCK;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, want));
+}
+
+int grid_tiles(const void* kern, int ntiles) { return std::max(1, std::min(resident_grid(kern, 0), ntiles)); }
+
+Csr csr_of(const gmresir_matrix* A, bool fp64) {
+  Csr c;
+  c.n = (int)A->n;
+  c.ntiles = A->ntiles;
+  c.rowptr = A->rowptr;
+  c.col = A->colidx;
+  c.vals = fp64 ? (const void*)A->vals64 : (const void*)A->vals32;
+  c.tile_row = A->tile_row;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+
+struct Layout {
+  size_t V, wtmp, w1, w2, r64, rhat, u, z, py, p0, p1, p2, part, hdr, arr, total;
+  long ldv;
+  int m;
+  int sT, sS;
+  bool multi, poly;
+};
+
+bool valid_params(const gmresir_params* p, const char** why) {
+  if (!p) return *why = "params is NULL", false;
+  if (p->restart < 1 || p->restart > MAX_RESTART) return *why = "restart must be in [1, 512]", false;
+  if (p->inner_cap < 0) return *why = "inner_cap must be >= 0", false;
+  if (p->max_iters <= 0) return *why = "max_iters must be > 0", false;
+  if (!(p->rtol > 0.0) || !isfinite(p->rtol)) return *why = "rtol must be finite and > 0", false;
+  if (p->inner_prec != GMRESIR_FP64 && p->inner_prec != GMRESIR_FP32) return *why = "inner_prec must be FP64 or FP32", false;
+  if (p->inner_prec == GMRESIR_FP64 && p->basis_prec != GMRESIR_FP64)
+    return *why = "an fp64 inner solve needs an fp64 basis", false;
+  if (p->inner_prec == GMRESIR_FP32 && p->basis_prec != GMRESIR_FP32 && p->basis_prec != GMRESIR_BF16)
+    return *why = "an fp32 inner solve needs an FP32 or BF16 basis", false;
+  if (p->poly_degree < 0 || p->poly_degree > 255) return *why = "poly_degree must be in [0, 255]", false;
+  if (p->check_mode != 0 && p->check_mode != 1) return *why = "check_mode must be 0 or 1", false;
+  if (p->profile != 0 && p->profile != 1) return *why = "profile must be 0 or 1", false;
+  if (p->reserved != 0) return *why = "reserved must be 0", false;
+  return true;
+}
+
+Layout make_layout(int64_t n, const gmresir_params* p) {
+  Layout L{};
+  L.m = p->restart;
+  L.sT = p->inner_prec == GMRESIR_FP64 ? 8 : 4;
+  L.sS = p->basis_prec == GMRESIR_FP64 ? 8 : p->basis_prec == GMRESIR_FP32 ? 4 : 2;
+  int cap = p->inner_cap == 0 ? p->restart : p->inner_cap;
+  L.multi = cap > p->restart;
+  L.poly = p->poly_degree > 0;
+  L.ldv = (long)((n + 127) / 128 * 128);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  size_t vecT = (size_t)n * L.sT;
+  L.V = take((size_t)L.ldv * (L.m + 1) * L.sS);
+  L.wtmp = take(vecT);
+  L.w1 = take(vecT);
+  L.w2 = take(vecT);
+  L.r64 = take((size_t)n * 8);
+  bool need_uz = L.multi || L.poly;
+  L.rhat = L.multi ? take(vecT) : 0;
+  L.u = L.multi ? take(vecT) : 0;
+  L.z = need_uz ? take(vecT) : 0;
+  L.py = L.poly ? take(vecT) : 0;
+  L.p0 = L.poly ? take(vecT) : 0;
+  L.p1 = L.poly ? take(vecT) : 0;
+  L.p2 = L.poly ? take(vecT) : 0;
+  L.part = take((size_t)MAX_BLOCKS * PSTRIDE * 8);
+  L.hdr = take(sizeof(StateHdr));
+  size_t m = L.m;
+  size_t arr = (2 * (m + 2) + 2 * (m + 1) * m + 2 * m + (m + 2) + 2 * m) * sizeof(double);
+  L.arr = take(arr);
+  L.total = o;
+  return L;
+}
+
+State state_of(char* ws, const Layout& L) {
+  State st;
+  st.hdr = (StateHdr*)(ws + L.hdr);
+  double* a = (double*)(ws + L.arr);
+  size_t m = L.m;
+  st.ld = (int)(m + 1);
+  st.h1 = a;
+  a += m + 2;
+  st.h2 = a;
+  a += m + 2;
+  st.Hbar = a;
+  a += (m + 1) * m;
+  st.R = a;
+  a += (m + 1) * m;
+  st.cs = a;
+  a += m;
+  st.sn = a;
+  a += m;
+  st.g = a;
+  a += m + 2;
+  st.y = a;
+  a += m;
+  st.hist = a;
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// profiling (HIP events around every launch) and algorithmic byte counts
+// ---------------------------------------------------------------------------
+
+struct Prof {
+  bool on = false;
+  hipStream_t stream = nullptr;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  size_t used = 0;
+  double t[GMRESIR_NCAT] = {0};
+  double bytes[GMRESIR_NCAT] = {0};
+  int64_t launches[GMRESIR_NCAT] = {0};
+  hipEvent_t take() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  template <typename F>
+  void run(int cat, double b, F&& launch) {
+    bytes[cat] += b;
+    launches[cat] += 1;
+    if (!on) {
+      launch();
+      return;
+    }
+    hipEvent_t e0 = take(), e1 = take();
+    if (e0) (void)hipEventRecord(e0, stream);
+    launch();
+    if (e1) (void)hipEventRecord(e1, stream);
+    if (e0 && e1) pending.push_back({cat, {e0, e1}});
+  }
+  // after a stream synchronisation
+  void flush() {
+    for (auto& p : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) t[p.first] += ms * 1e-3;
+    }
+    pending.clear();
+    used = 0;
+  }
+  ~Prof() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// polynomial program: the product form of p(A) as a list of SpMV steps
+// ---------------------------------------------------------------------------
+
+enum PBuf { PB_SRC = 0, PB_P0, PB_P1, PB_P2, PB_NONE };
+
+struct PStep {
+  int x, w, d;  // gathered source, own-row auxiliary vector, output vector (PB_*)
+  bool has_y, y_read;
+  double ay, aw, ax, at, bw, bx, bt;
+};
+
+// roots: nr (re, im) pairs in application order, conjugate pairs adjacent.
+// y accumulates p(A) src; see the oracle-independent derivation in the
+// Python package's documentation of the product form.
+bool build_poly_program(int nr, const double* roots, std::vector<PStep>& prog, const char** why) {
+  prog.clear();
+  if (nr < 2) return *why = "a polynomial preconditioner needs at least 2 roots", false;
+  int cur = PB_SRC;
+  auto other = [](int b) { return b == PB_P0 ? PB_P1 : PB_P0; };
+  bool y_has = false;
+  int i = 0;
+  while (i < nr) {
+    const double re = roots[2 * i], im = roots[2 * i + 1];
+    if (im == 0.0) {
+      if (re == 0.0 || !isfinite(re)) return *why = "polynomial root is zero or not finite", false;
+      if (i == nr - 1) {
+        // last root: y += d_prev / theta, folded into the previous step
+        PStep& p = prog.back();
+        const double inv = 1.0 / re;
+        if (!p.has_y) {
+          p.has_y = true;
+          p.y_read = y_has;
+          p.ay = 1.0;
+          p.aw = p.ax = p.at = 0.0;
+        }
+        p.aw += p.bw * inv;
+        p.ax += p.bx * inv;
+        p.at += p.bt * inv;
+        p.d = PB_NONE;
+        i += 1;
+      } else {
+        PStep s{};
+        s.x = cur;
+        s.w = PB_NONE;
+        s.has_y = true;
+        s.y_read = y_has;
+        s.ay = 1.0;
+        s.ax = 1.0 / re;
+        s.d = other(cur);
+        s.bx = 1.0;
+        s.bt = -1.0 / re;
+        prog.push_back(s);
+        cur = s.d;
+        y_has = true;
+        i += 1;
+      }
+    } else {
+      if (i + 1 >= nr || roots[2 * (i + 1)] != re || roots[2 * (i + 1) + 1] != -im)
+        return *why = "complex roots must come in adjacent conjugate pairs", false;
+      const double mu = re * re + im * im;
+      const bool last = (i + 2 == nr);
+      PStep a{};
+      a.x = cur;
+      a.w = PB_NONE;
+      a.has_y = true;
+      a.y_read = y_has;
+      a.ay = 1.0;
+      a.ax = 2.0 * re / mu;
+      a.at = -1.0 / mu;
+      a.d = last ? PB_NONE : PB_P2;
+      a.bt = 1.0;
+      prog.push_back(a);
+      y_has = true;
+      if (!last) {
+        PStep b{};
+        b.x = PB_P2;
+        b.w = cur;
+        b.has_y = false;
+        b.d = other(cur);
+        b.bw = 1.0;
+        b.bx = -2.0 * re / mu;
+        b.bt = 1.0 / mu;
+        prog.push_back(b);
+        cur = b.d;
+      }
+      i += 2;
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// the solver context
+// ---------------------------------------------------------------------------
+
+template <typename T, typename S>
+struct Ctx {
+  const gmresir_matrix* A;
+  hipStream_t stream;
+  Layout L;
+  char* ws;
+  State st;
+  S* V;
+  T *wtmp, *w1, *w2, *rhat, *u, *z, *py, *p0, *p1, *p2;
+  double* r64;
+  T* part;
+  int n;
+  Csr Ain;  // matrix in inner precision
+  Csr A64;
+  Prof* prof;
+  std::vector<PStep> prog;
+  bool poly_on = false;  // inner operator is A p(A)
+
+
+  Ctx(const gmresir_matrix* A_, char* ws_, const Layout& L_, hipStream_t s, Prof* pr) : A(A_), stream(s), L(L_), ws(ws_), prof(pr) {
+    st = state_of(ws, L);
+    V = (S*)(ws + L.V);
+    wtmp = (T*)(ws + L.wtmp);
+    w1 = (T*)(ws + L.w1);
+    w2 = (T*)(ws + L.w2);
+    r64 = (double*)(ws + L.r64);
+    rhat = L.multi ? (T*)(ws + L.rhat) : nullptr;
+    u = L.multi ? (T*)(ws + L.u) : nullptr;
+    z = (L.multi || L.poly) ? (T*)(ws + L.z) : nullptr;
+    py = L.poly ? (T*)(ws + L.py) : nullptr;
+    p0 = L.poly ? (T*)(ws + L.p0) : nullptr;
+    p1 = L.poly ? (T*)(ws + L.p1) : nullptr;
+    p2 = L.poly ? (T*)(ws + L.p2) : nullptr;
+    part = (T*)(ws + L.part);
+    n = (int)A->n;
+    Ain = csr_of(A, sizeof(T) == 8);
+    A64 = csr_of(A, true);
+  }
+
+  double sT() const { return (double)sizeof(T); }
+  double sS() const { return (double)sizeof(S); }
+  double spmv_bytes() const { return (sT() + 4.0) * A->nnz + 4.0 * (A->n + 1); }
+
+  T* buf(int b, T* src) {
+    switch (b) {
+      case PB_SRC: return src;
+      case PB_P0: return p0;
+      case PB_P1: return p1;
+      case PB_P2: return p2;
+      default: return nullptr;
+    }
+  }
+
+  // y_out = p(A) src; scaled: src holds the unnormalised next basis vector
+  // (wtmp, scaled by inv_h and rounded to the basis type, written into V[:, j]).
+  void run_poly(T* src, bool scaled, int j, T* y_out, int check_done, int cat) {
+    for (size_t s = 0; s < prog.size(); ++s) {
+      const PStep& ps = prog[s];
+      PolyCoef<T> cf;
+      cf.ay = (T)ps.ay;
+      cf.aw = (T)ps.aw;
+      cf.ax = (T)ps.ax;
+      cf.at = (T)ps.at;
+      cf.bw = (T)ps.bw;
+      cf.bx = (T)ps.bx;
+      cf.bt = (T)ps.bt;
+      cf.has_y = ps.has_y;
+      cf.y_read = ps.y_read;
+      cf.has_d = ps.d != PB_NONE;
+      cf.has_w = ps.w != PB_NONE;
+      T* X = buf(ps.x, src);
+      T* W = buf(ps.w, src);
+      T* D = buf(ps.d, src);
+      const int w_scaled = (scaled && ps.w == PB_SRC) ? 1 : 0;
+      const int write_v = (scaled && s == 0) ? 1 : 0;
+      double b = spmv_bytes() + sT() * n * (1 + (ps.has_y ? 1 : 0) + (ps.y_read ? 1 : 0) + (cf.has_w ? 1 : 0) +
+                                            (cf.has_d ? 1 : 0)) +
+                 (write_v ? sS() * n : 0.0);
+      if (scaled && ps.x == PB_SRC) {
+        auto kern = k_poly_step<T, S, true>;
+        int g = grid_tiles((const void*)kern, Ain.ntiles);
+        prof->run(cat, b, [&] {
+          hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, Ain, X, V, L.ldv, j, write_v, W, w_scaled, y_out, D,
+                             cf, st, check_done);
+        });
+      } else {
+        auto kern = k_poly_step<T, S, false>;
+        int g = grid_tiles((const void*)kern, Ain.ntiles);
+        prof->run(cat, b, [&] {
+          hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, Ain, X, V, L.ldv, j, 0, W, w_scaled, y_out, D, cf,
+                             st, check_done);
+        });
+      }
+    }
+  }
+
+  template <int SLOTS, bool SCALED>
+  void launch_spmv_proj(const T* src, int j) {
+    constexpr int KMAX = NWAVES * SLOTS;
+    auto kern = k_spmv_proj<T, S, SLOTS, SCALED>;
+    int g = grid_tiles((const void*)kern, Ain.ntiles);
+    const int C = std::min(j + 1, KMAX);
+    // basis columns read from memory: all handled columns but the new one (SCALED)
+    const int nread = SCALED ? std::min(j, C) : C;
+    double b = spmv_bytes() + sT() * n * 2 + sS() * n * nread + (SCALED ? sS() * n : 0.0);
+    prof->run(GMRESIR_CAT_SPMV_PROJ, b, [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, Ain, src, V, L.ldv, j, w1, st, part);
+    });
+    reduce_h(GMRESIR_CAT_SPMV_PROJ, g, C, st.h1, -1);
+  }
+
+  void reduce_h(int cat, int producer_grid, int nv, double* h, int last_to) {
+    auto kern = k_reduce_h<T>;
+    prof->run(cat, 0.0, [&] {
+      hipLaunchKernelGGL(kern, dim3(1), dim3(512), 0, stream, (const T*)part, nv, producer_grid, h, last_to, st, 1);
+    });
+  }
+
+  template <bool SCALED>
+  void spmv_proj_dispatch(const T* src, int j) {
+    const int k = j + 1;
+    if (k <= 16) launch_spmv_proj<4, SCALED>(src, j);
+    else if (k <= 32) launch_spmv_proj<8, SCALED>(src, j);
+    else if (k <= 64) launch_spmv_proj<16, SCALED>(src, j);
+    else launch_spmv_proj<32, SCALED>(src, j);
+    // columns beyond the fused limit (V[:, j] is in memory by now)
+    for (int c0 = 128; c0 < k; c0 += 64) dots(c0, std::min(64, k - c0), w1, st.h1, GMRESIR_CAT_OTHER);
+  }
+
+  void dots(int c0, int nc, const T* w, double* h, int cat) {
+    auto kern = k_dots<T, S>;
+    int g = grid_rows((const void*)kern, n);
+    prof->run(cat, sS() * n * nc + sT() * n, [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, V, L.ldv, c0, nc, w, st, 1, part);
+    });
+    reduce_h(cat, g, nc, h + c0, -1);
+  }
+
+  template <int KREG, int KACC>
+  void launch_update_proj(int k) {
+    auto kern = k_update_proj<T, S, KREG, KACC>;
+    int g = grid_rows((const void*)kern, n);
+    prof->run(GMRESIR_CAT_UPDATE_PROJ, sT() * n * 2 + sS() * n * k, [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w1, w2, V, L.ldv, k, st, part);
+    });
+    reduce_h(GMRESIR_CAT_UPDATE_PROJ, g, k, st.h2, -1);
+  }
+
+  void update_proj_dispatch(int k) {
+    bool fused = true;
+    if (k <= 16) launch_update_proj<16, 16>(k);
+    else if (k <= 32) launch_update_proj<32, 32>(k);
+    else if constexpr (sizeof(T) == 8) {
+      if (k <= 56) launch_update_proj<16, 56>(k);
+      else fused = false;
+    } else {
+      if (k <= 64) launch_update_proj<64, 64>(k);
+      else if (k <= 128) launch_update_proj<32, 128>(k);
+      else fused = false;
+    }
+    if (!fused) {
+      auto kern = k_update<T, S>;
+      int g = grid_rows((const void*)kern, n);
+      prof->run(GMRESIR_CAT_OTHER, sT() * n * 2 + sS() * n * k, [&] {
+        hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w1, w2, V, L.ldv, k, (const double*)st.h1, st);
+      });
+      for (int c0 = 0; c0 < k; c0 += 64) dots(c0, std::min(64, k - c0), w2, st.h2, GMRESIR_CAT_OTHER);
+    }
+  }
+
+  void update_norm(int j, int kmax) {
+    auto kern = k_update_norm<T, S>;
+    int g = grid_rows((const void*)kern, n);
+    prof->run(GMRESIR_CAT_UPDATE_NORM, sT() * n * 2 + sS() * n * (j + 1), [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w2, wtmp, V, L.ldv, j, st, part);
+    });
+    auto tail = k_norm_givens<T>;
+    prof->run(GMRESIR_CAT_UPDATE_NORM, 0.0, [&] {
+      hipLaunchKernelGGL(tail, dim3(1), dim3(BLOCK), 0, stream, (const T*)part, g, st, j, kmax);
+    });
+  }
+
+  // one inner iteration j of a cycle of at most kmax steps
+  void iteration(int j, int kmax) {
+    if (poly_on) {
+      run_poly(wtmp, true, j, z, 1, GMRESIR_CAT_POLY);
+      spmv_proj_dispatch<false>(z, j);
+    } else {
+      spmv_proj_dispatch<true>(wtmp, j);
+    }
+    update_proj_dispatch(j + 1);
+    update_norm(j, kmax);
+  }
+
+  void backsolve(int kmax) {
+    auto kern = k_backsolve<T>;
+    size_t tri = (size_t)kmax * (kmax + 1) / 2 * sizeof(T);
+    size_t smem = (size_t)(((kmax + 1) & ~1) + 2) * sizeof(T) + std::min<size_t>(40960, tri);
+    prof->run(GMRESIR_CAT_REFINE, 0.0, [&] {
+      hipLaunchKernelGGL(kern, dim3(1), dim3(BLOCK), smem, stream, st);
+    });
+  }
+
+  void init(double rtol, int check_mode, double gamma0) {
+    prof->run(GMRESIR_CAT_REFINE, 0.0, [&] {
+      hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, stream, st, rtol, check_mode, gamma0);
+    });
+  }
+
+  void norm64(const double* v, double* dst) {
+    auto kern = k_norm64;
+    int g = grid_rows((const void*)kern, n);
+    prof->run(GMRESIR_CAT_REFINE, 8.0 * n, [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, v, (double*)part);
+    });
+    sqrt_tail(g, dst);
+  }
+
+  void sqrt_tail(int producer_grid, double* dst) {
+    prof->run(GMRESIR_CAT_REFINE, 0.0, [&] {
+      hipLaunchKernelGGL(k_sqrt_tail, dim3(1), dim3(BLOCK), 0, stream, (const double*)part, producer_grid, dst);
+    });
+  }
+
+  void cycle_tail(int producer_grid) {
+    auto kern = k_cycle_tail<T>;
+    prof->run(GMRESIR_CAT_REFINE, 0.0, [&] {
+      hipLaunchKernelGGL(kern, dim3(1), dim3(BLOCK), 0, stream, (const T*)part, producer_grid, st);
+    });
+  }
+
+  void resid64(const double* x, const double* b) {
+    auto kern = k_resid64;
+    int g = grid_tiles((const void*)kern, A64.ntiles);
+    prof->run(GMRESIR_CAT_REFINE, 12.0 * A->nnz + 4.0 * (A->n + 1) + 8.0 * n * 3, [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, A64, x, b, r64, (double*)part);
+    });
+    sqrt_tail(g, &st.hdr->gamma);
+  }
+
+  void cast(const double* r) {
+    auto kern = k_cast<T>;
+    int g = grid_rows((const void*)kern, n);
+    prof->run(GMRESIR_CAT_REFINE, 8.0 * n + sT() * n * (rhat ? 2 : 1), [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, r, wtmp, rhat, st, part);
+    });
+    cycle_tail(g);
+  }
+
+  void correct_x(double* x, int kmax) {
+    auto kern = k_correct_x<T, S>;
+    int g = grid_rows((const void*)kern, n);
+    prof->run(GMRESIR_CAT_REFINE, sS() * n * kmax + 16.0 * n, [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, V, L.ldv, st, x);
+    });
+  }
+
+  void vy(T* out, int kmax) {
+    auto kern = k_vy<T, S>;
+    int g = grid_rows((const void*)kern, n);
+    prof->run(GMRESIR_CAT_REFINE, sS() * n * kmax + sT() * n, [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, V, L.ldv, st, out);
+    });
+  }
+
+  void accum(const T* zz, T* uu, int first) {
+    auto kern = k_accum<T>;
+    int g = grid_rows((const void*)kern, n);
+    prof->run(GMRESIR_CAT_REFINE, sT() * n * (first ? 2 : 3), [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, zz, uu, first);
+    });
+  }
+
+  void axpy_x(const T* uu, double* x) {
+    auto kern = k_axpy_x<T>;
+    int g = grid_rows((const void*)kern, n);
+    prof->run(GMRESIR_CAT_REFINE, sT() * n + 16.0 * n, [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, uu, st, x);
+    });
+  }
+
+  void inner_resid() {
+    auto kern = k_inner_resid<T>;
+    int g = grid_tiles((const void*)kern, Ain.ntiles);
+    prof->run(GMRESIR_CAT_REFINE, spmv_bytes() + sT() * n * 3, [&] {
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, Ain, (const T*)u, (const T*)rhat, wtmp, part);
+    });
+    cycle_tail(g);
+  }
+
+  int read_hdr(StateHdr* h) {
+    HIP_TRY(hipMemcpyAsync(h, st.hdr, sizeof(StateHdr), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipGetLastError());
+    prof->flush();
+    return 0;
+  }
+};
+
+// --------------------------------------------------------------------------
+// the refinement loop (Algorithm 2; with an fp64 inner solve and one cycle
+// per refinement it is restarted GMRES(m), Algorithm 1)
+// --------------------------------------------------------------------------
+
+template <typename T, typename S>
+int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresir_params* p,
+               const double* roots, char* ws, const Layout& L, gmresir_result* res, double* hist, int64_t hist_cap,
+               hipStream_t stream) {
+  Prof prof;
+  prof.on = p->profile == 1;
+  prof.stream = stream;
+  Ctx<T, S> c(A, ws, L, stream, &prof);
+  if (L.poly) {
+    const char* why = "";
+    if (!build_poly_program(p->poly_degree + 1, roots, c.prog, &why)) {
+      set_error("%s", why);
+      return GMRESIR_ERR_INVALID_ARG;
+    }
+    c.poly_on = true;
+  }
+  const int m = p->restart;
+  const int cap = p->inner_cap == 0 ? m : p->inner_cap;
+  const bool single = cap <= m;
+  int64_t hist_n = 0;
+
+  c.init(p->rtol, p->check_mode, 0.0);
+  c.norm64(b, &c.st.hdr->beta);
+  c.resid64(x, b);
+  c.cast(c.r64);
+  StateHdr H;
+  if (int e = c.read_hdr(&H)) return e;
+  const double beta = H.beta;
+  double gamma = H.gamma;
+  int status = GMRESIR_OK;
+  if (!isfinite(beta)) {
+    set_error("||b|| is not finite");
+    status = GMRESIR_ERR_NUMERIC;
+  }
+  if (status == GMRESIR_OK && beta == 0.0) {
+    int g = grid_rows((const void*)k_fill64, c.n);
+    hipLaunchKernelGGL(k_fill64, dim3(g), dim3(BLOCK), 0, stream, c.n, x, 0.0);
+    HIP_TRY(hipStreamSynchronize(stream));
+    res->rel_resid_true = 0.0;
+    res->rel_resid_implicit = 0.0;
+    return GMRESIR_OK;
+  }
+  double best = gamma;
+  int stall = 0;
+  double implicit_rel = gamma / beta;
+  while (status == GMRESIR_OK) {
+    const double rel = gamma / beta;
+    if (!isfinite(rel)) {
+      set_error("non-finite residual after %d refinements: ||r|| = %g, ||b|| = %g", res->refinements, gamma, beta);
+      status = GMRESIR_ERR_NUMERIC;
+      break;
+    }
+    if (rel <= p->rtol) break;
+    if (res->iters >= p->max_iters) {
+      status = GMRESIR_NOT_CONVERGED;
+      break;
+    }
+    const int64_t budget = std::min<int64_t>(cap, p->max_iters - res->iters);
+    int64_t used = 0;
+    bool numeric = false;
+    int first = 1;
+    while (used < budget) {
+      const int kmax = (int)std::min<int64_t>(m, budget - used);
+      for (int j = 0; j < kmax; ++j) c.iteration(j, kmax);
+      c.backsolve(kmax);
+      if (single && !L.poly) {
+        c.correct_x(x, kmax);
+      } else {
+        c.vy(c.z, kmax);
+        T* upart = c.z;
+        if (L.poly) {
+          c.run_poly(c.z, false, 0, c.py, 0, GMRESIR_CAT_REFINE);
+          upart = c.py;
+        }
+        if (single) c.axpy_x(upart, x);
+        else c.accum(upart, c.u, first);
+      }
+      if (single) {
+        used = -1;  // read after the residual
+        break;
+      }
+      if (int e = c.read_hdr(&H)) return e;
+      res->cycles += 1;
+      const int kc = H.cycle_k;
+      if (hist && hist_n < hist_cap && kc > 0) {
+        int64_t cnt = std::min<int64_t>(kc, hist_cap - hist_n);
+        HIP_TRY(hipMemcpy(hist + hist_n, c.st.hist, cnt * sizeof(double), hipMemcpyDeviceToHost));
+        hist_n += cnt;
+      }
+      used += kc;
+      if (H.cycle_flags & F_NUMERIC) {
+        set_error("NaN/Inf in inner cycle %lld: k=%d flags=%d gamma_in=%.3e", (long long)res->cycles, kc,
+                  H.cycle_flags, H.gamma_in);
+        numeric = true;
+        break;
+      }
+      implicit_rel = H.implicit * gamma / beta;
+      if ((H.cycle_flags & (F_STOPPED | F_BREAKDOWN)) || kc == 0 || used >= budget) break;
+      c.inner_resid();
+      first = 0;
+    }
+    if (numeric) {
+      status = GMRESIR_ERR_NUMERIC;
+      break;
+    }
+    if (!single) c.axpy_x(c.u, x);
+    c.resid64(x, b);
+    c.cast(c.r64);
+    const double gamma_old = gamma;
+    if (int e = c.read_hdr(&H)) return e;
+    if (single) {
+      res->cycles += 1;
+      const int kc = H.cycle_k;
+      if (hist && hist_n < hist_cap && kc > 0) {
+        int64_t cnt = std::min<int64_t>(kc, hist_cap - hist_n);
+        HIP_TRY(hipMemcpy(hist + hist_n, c.st.hist, cnt * sizeof(double), hipMemcpyDeviceToHost));
+        hist_n += cnt;
+      }
+      used = kc;
+      if (H.cycle_flags & F_NUMERIC) {
+        set_error("NaN/Inf in inner cycle %lld (refinement %d): cycle k=%d flags=%d gamma=%.3e gamma_in=%.3e",
+                  (long long)res->cycles, res->refinements, kc, H.cycle_flags, gamma_old, H.gamma_in);
+        status = GMRESIR_ERR_NUMERIC;
+        res->iters += used;
+        break;
+      }
+      implicit_rel = H.implicit * gamma_old / beta;
+    }
+    res->iters += used;
+    res->refinements += 1;
+    gamma = H.gamma;
+    if (gamma < best) {
+      best = gamma;
+      stall = 0;
+    } else if (++stall >= 3) {
+      status = GMRESIR_STAGNATED;
+      break;
+    }
+  }
+  res->rel_resid_true = gamma / beta;
+  res->rel_resid_implicit = implicit_rel;
+  for (int i = 0; i < GMRESIR_NCAT; ++i) {
+    res->cat_time_s[i] = prof.t[i];
+    res->cat_bytes[i] = prof.bytes[i];
+    res->cat_launches[i] = prof.launches[i];
+  }
+  return status;
+}
+
+// fp32 Arnoldi process of `steps` steps from the fp64 vector src (scaled to
+// unit norm in fp32); fills the header and the unrotated Hessenberg matrix.
+int arnoldi32(const gmresir_matrix* A, const double* src, int steps, char* ws, const Layout& L, hipStream_t stream,
+              StateHdr* H, std::vector<double>* hbar, std::vector<double>* hist) {
+  Prof prof;
+  prof.stream = stream;
+  Ctx<float, float> c(A, ws, L, stream, &prof);
+  c.init(0.0, 0, 1.0);
+  c.cast(src);
+  for (int j = 0; j < steps; ++j) c.iteration(j, steps);
+  if (int e = c.read_hdr(H)) return e;
+  if (hbar) {
+    hbar->assign((size_t)(steps + 1) * c.st.ld, 0.0);
+    HIP_TRY(hipMemcpy(hbar->data(), c.st.Hbar, (size_t)steps * c.st.ld * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  if (hist) {
+    hist->assign(steps, 0.0);
+    HIP_TRY(hipMemcpy(hist->data(), c.st.hist, steps * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return 0;
+}
+
+Layout arnoldi_layout(int64_t n, int steps, bool poly) {
+  gmresir_params q{};
+  q.restart = std::max(steps, 1);
+  q.inner_cap = 0;
+  q.max_iters = 1;
+  q.rtol = 1.0;
+  q.inner_prec = GMRESIR_FP32;
+  q.basis_prec = GMRESIR_FP32;
+  q.poly_degree = poly ? 1 : 0;
+  return make_layout(n, &q);
+}
+
+bool ws_ok(const void* ws, size_t have, size_t need) {
+  if (!ws) return set_error("workspace is NULL"), false;
+  if (((uintptr_t)ws) % ALIGN) return set_error("workspace must be 256-byte aligned"), false;
+  if (have < need) return set_error("workspace has %zu bytes, %zu needed", have, need), false;
+  return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+int32_t gmresir_abi_version(void) { return 1; }
+
+const char* gmresir_last_error(void) { return gir::last_error(); }
+
+const char* gmresir_status_string(int status) {
+  switch (status) {
+    case GMRESIR_OK: return "ok";
+    case GMRESIR_NOT_CONVERGED: return "not converged (max_iters reached)";
+    case GMRESIR_STAGNATED: return "stagnated (residual did not decrease over 3 restarts)";
+    case GMRESIR_BREAKDOWN: return "Arnoldi breakdown before the requested number of steps";
+    case GMRESIR_ERR_INVALID_ARG: return "invalid argument";
+    case GMRESIR_ERR_HIP: return "HIP runtime error";
+    case GMRESIR_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case GMRESIR_ERR_NUMERIC: return "NaN or Inf encountered";
+    case GMRESIR_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+size_t gmresir_matrix_storage_bytes(int64_t n, int64_t nnz) {
+  if (n < 1 || nnz < 0 || nnz >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31)) return 0;
+  return align_up((size_t)nnz * 4) + align_up((size_t)(max_tiles(n, nnz) + 1) * 4);
+}
+
+int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx, const double* vals,
+                          void* storage, size_t storage_bytes, void* stream, gmresir_matrix** out) {
+  if (!out || !rowptr || (nnz > 0 && (!colidx || !vals)) || !storage) {
+    set_error("gmresir_matrix_create: NULL pointer argument");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  size_t need = gmresir_matrix_storage_bytes(n, nnz);
+  if (need == 0) {
+    set_error("gmresir_matrix_create: invalid sizes n=%lld nnz=%lld", (long long)n, (long long)nnz);
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (!ws_ok(storage, storage_bytes, need)) return GMRESIR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> rp(n + 1);
+  HIP_TRY(hipMemcpyAsync(rp.data(), rowptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (rp[0] != 0 || rp[n] != nnz) {
+    set_error("gmresir_matrix_create: rowptr[0] must be 0 and rowptr[n] == nnz");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) {
+      set_error("gmresir_matrix_create: rowptr decreases at row %lld", (long long)i);
+      return GMRESIR_ERR_INVALID_ARG;
+    }
+  // greedy cut into tiles of <= TILE_ROWS rows and <= TILE_NNZ nonzeros
+  std::vector<int32_t> tiles;
+  tiles.push_back(0);
+  int64_t r0 = 0;
+  while (r0 < n) {
+    int64_t r = r0;
+    while (r < n && r - r0 < TILE_ROWS && (int64_t)rp[r + 1] - rp[r0] <= TILE_NNZ) ++r;
+    if (r == r0) {
+      r = r0 + 1;  // one row longer than a tile
+    } else if (r < n && (r & 3) && (r & ~(int64_t)3) > r0) {
+      r &= ~(int64_t)3;  // end tiles on a multiple of 4 rows (16-byte basis loads)
+    }
+    tiles.push_back((int32_t)r);
+    r0 = r;
+  }
+  const int ntiles = (int)tiles.size() - 1;
+  if (ntiles > max_tiles(n, nnz)) {
+    set_error("internal: tile bound exceeded");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  char* st = (char*)storage;
+  float* v32 = (float*)st;
+  int32_t* tr = (int32_t*)(st + align_up((size_t)nnz * 4));
+  HIP_TRY(hipMemcpyAsync(tr, tiles.data(), tiles.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (nnz > 0) {
+    int g = (int)std::min<int64_t>(4096, (nnz + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_cast_vals, dim3(g), dim3(BLOCK), 0, s, nnz, vals, v32);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  gmresir_matrix* A = new gmresir_matrix;
+  A->n = n;
+  A->nnz = nnz;
+  A->rowptr = rowptr;
+  A->colidx = colidx;
+  A->vals64 = vals;
+  A->vals32 = v32;
+  A->tile_row = tr;
+  A->ntiles = ntiles;
+  A->device = 0;
+  (void)hipGetDevice(&A->device);
+  *out = A;
+  return GMRESIR_OK;
+}
+
+int gmresir_matrix_destroy(gmresir_matrix* A) {
+  delete A;
+  return GMRESIR_OK;
+}
+
+int64_t gmresir_matrix_n(const gmresir_matrix* A) { return A ? A->n : -1; }
+int64_t gmresir_matrix_nnz(const gmresir_matrix* A) { return A ? A->nnz : -1; }
+int64_t gmresir_matrix_tiles(const gmresir_matrix* A) { return A ? A->ntiles : -1; }
+
+int gmresir_spmv(const gmresir_matrix* A, int32_t prec, const void* x, void* y, void* stream) {
+  if (!A || !x || !y) {
+    set_error("gmresir_spmv: NULL argument");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (x == y) {
+    set_error("gmresir_spmv: x and y must not overlap");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == GMRESIR_FP64) {
+    auto kern = k_spmv<double>;
+    int g = grid_tiles((const void*)kern, A->ntiles);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, s, csr_of(A, true), (const double*)x, (double*)y);
+  } else if (prec == GMRESIR_FP32) {
+    auto kern = k_spmv<float>;
+    int g = grid_tiles((const void*)kern, A->ntiles);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, s, csr_of(A, false), (const float*)x, (float*)y);
+  } else {
+    set_error("gmresir_spmv: prec must be FP64 or FP32");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  HIP_TRY(hipGetLastError());
+  return GMRESIR_OK;
+}
+
+size_t gmresir_workspace_bytes(const gmresir_matrix* A, const gmresir_params* p) {
+  const char* why = "";
+  if (!A || !valid_params(p, &why)) return 0;
+  return make_layout(A->n, p).total;
+}
+
+int gmresir_solve(const gmresir_matrix* A, const double* b, double* x, const gmresir_params* p,
+                  const double* poly_roots, void* ws, size_t ws_bytes, gmresir_result* res, double* hist,
+                  int64_t hist_cap, void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  const char* why = "";
+  if (!A || !b || !x || !res) {
+    set_error("gmresir_solve: NULL argument");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (!valid_params(p, &why)) {
+    set_error("gmresir_solve: %s", why);
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (p->poly_degree > 0 && !poly_roots) {
+    set_error("gmresir_solve: poly_degree > 0 needs poly_roots_host");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (hist_cap < 0 || (hist_cap > 0 && !hist)) {
+    set_error("gmresir_solve: bad history buffer");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  Layout L = make_layout(A->n, p);
+  if (!ws_ok(ws, ws_bytes, L.total)) return GMRESIR_ERR_WORKSPACE;
+  memset(res, 0, sizeof(*res));
+  hipStream_t s = (hipStream_t)stream;
+  int st;
+  if (p->inner_prec == GMRESIR_FP64)
+    st = solve_impl<double, double>(A, b, x, p, poly_roots, (char*)ws, L, res, hist, hist_cap, s);
+  else if (p->basis_prec == GMRESIR_FP32)
+    st = solve_impl<float, float>(A, b, x, p, poly_roots, (char*)ws, L, res, hist, hist_cap, s);
+  else
+    st = solve_impl<float, bf16_t>(A, b, x, p, poly_roots, (char*)ws, L, res, hist, hist_cap, s);
+  res->status = st;
+  res->solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+size_t gmresir_poly_workspace_bytes(const gmresir_matrix* A, int32_t max_degree) {
+  if (!A || max_degree < 0 || max_degree > 255) return 0;
+  return arnoldi_layout(A->n, std::max(max_degree + 1, 10), true).total;
+}
+
+int gmresir_poly_setup(const gmresir_matrix* A, int32_t degree, const double* start, uint64_t seed, void* ws,
+                       size_t ws_bytes, double* roots, double* hbar_host, void* stream) {
+  if (!A || !roots || degree < 1 || degree > 255) {
+    set_error("gmresir_poly_setup: NULL argument or degree outside [1, 255]");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  const int steps = degree + 1;
+  Layout L = arnoldi_layout(A->n, std::max(steps, 10), true);
+  if (!ws_ok(ws, ws_bytes, L.total)) return GMRESIR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const double* src = start;
+  if (!src) {
+    double* r64 = (double*)((char*)ws + L.r64);
+    int g = (int)std::min<int64_t>(4096, (A->n + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_start_vector, dim3(g), dim3(BLOCK), 0, s, (int)A->n, seed, r64);
+    HIP_TRY(hipGetLastError());
+    src = r64;
+  }
+  StateHdr H;
+  std::vector<double> hb;
+  if (int e = arnoldi32(A, src, steps, (char*)ws, L, s, &H, &hb, nullptr)) return e;
+  if (H.flags & F_NUMERIC) {
+    set_error("gmresir_poly_setup: NaN/Inf in the Arnoldi process");
+    return GMRESIR_ERR_NUMERIC;
+  }
+  const int ld = L.m + 1;
+  if (hbar_host)
+    for (int jj = 0; jj < steps; ++jj)
+      for (int i = 0; i < steps + 1; ++i) hbar_host[(size_t)jj * (steps + 1) + i] = hb[(size_t)jj * ld + i];
+  if (H.k < steps) {
+    set_error("gmresir_poly_setup: Arnoldi breakdown after %d of %d steps", H.k, steps);
+    return GMRESIR_BREAKDOWN;
+  }
+  if (harmonic_ritz_leja(steps, hb.data(), ld, roots) != 0) {
+    set_error("gmresir_poly_setup: harmonic Ritz computation failed (singular H or no QR convergence)");
+    return GMRESIR_ERR_NUMERIC;
+  }
+  return GMRESIR_OK;
+}
+
+int gmresir_poly_apply(const gmresir_matrix* A, int32_t degree, const double* roots, const float* v, float* y,
+                       void* ws, size_t ws_bytes, void* stream) {
+  if (!A || !roots || !v || !y || degree < 1 || degree > 255 || (const void*)v == (void*)y) {
+    set_error("gmresir_poly_apply: bad arguments");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  Layout L = arnoldi_layout(A->n, std::max(degree + 1, 10), true);
+  if (!ws_ok(ws, ws_bytes, L.total)) return GMRESIR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  Prof prof;
+  Ctx<float, float> c(A, (char*)ws, L, s, &prof);
+  const char* why = "";
+  if (!build_poly_program(degree + 1, roots, c.prog, &why)) {
+    set_error("gmresir_poly_apply: %s", why);
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  c.init(0.0, 0, 1.0);
+  c.run_poly((float*)v, false, 0, y, 0, GMRESIR_CAT_POLY);
+  HIP_TRY(hipGetLastError());
+  return GMRESIR_OK;
+}
+
+int gmresir_features(const gmresir_matrix* A, const double* b, void* ws, size_t ws_bytes, float* feat, void* stream) {
+  if (!A || !b || !feat) {
+    set_error("gmresir_features: NULL argument");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  const int steps = 10;
+  Layout L = arnoldi_layout(A->n, steps, true);
+  if (!ws_ok(ws, ws_bytes, L.total)) return GMRESIR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  State st = state_of((char*)ws, L);
+  // row statistics (the r64 buffer holds the 10 results)
+  double* out = (double*)((char*)ws + L.r64);
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, 0.0, 0, 1.0);
+  {
+    auto kern = k_rowstats;
+    int g = grid_rows((const void*)kern, A->n);
+    double* part = (double*)((char*)ws + L.part);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, s, csr_of(A, true), part);
+    hipLaunchKernelGGL(k_rowstats_tail, dim3(1), dim3(BLOCK), 0, s, (const double*)part, g, out);
+  }
+  HIP_TRY(hipGetLastError());
+  double rs[10];
+  HIP_TRY(hipMemcpyAsync(rs, out, sizeof(rs), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  StateHdr H;
+  std::vector<double> hb, hist;
+  if (int e = arnoldi32(A, b, steps, (char*)ws, L, s, &H, &hb, &hist)) return e;
+  const double n = (double)A->n;
+  const double TINY = 1e-30;
+  auto lg = [&](double v) { return log10(std::max(v, TINY)); };
+  const double D = rs[9] / n;
+  double f[16] = {0};
+  f[0] = log10(n);
+  f[1] = (double)A->nnz / n;
+  f[2] = rs[8];
+  f[3] = rs[0] / n;
+  f[4] = rs[1];
+  f[5] = rs[2] / n;
+  f[6] = (rs[3] / n) / std::max(D, TINY);
+  f[7] = lg(sqrt(rs[4]) / sqrt(n));
+  const double mean = rs[5] / n;
+  f[8] = sqrt(std::max(0.0, rs[6] / n - mean * mean)) / std::max(D, TINY);
+  f[9] = rs[7] / n;
+  const int k = (H.flags & F_NUMERIC) ? 0 : H.k;
+  if (k > 0) {
+    f[10] = lg(hist[std::min(5, k) - 1]);
+    f[11] = lg(hist[k - 1]);
+    const int ld = L.m + 1;
+    std::vector<double> a((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+      for (int jj = 0; jj < k; ++jj) a[(size_t)i * k + jj] = (i > jj + 1) ? 0.0 : hb[(size_t)jj * ld + i];
+    std::vector<double> wr(k), wi(k);
+    if (hessenberg_eigvals(k, a, wr.data(), wi.data()) == 0) {
+      double amax = 0, amin = INFINITY, imax = 0, remin = INFINITY;
+      for (int i = 0; i < k; ++i) {
+        const double mod = hypot(wr[i], wi[i]);
+        amax = std::max(amax, mod);
+        amin = std::min(amin, mod);
+        imax = std::max(imax, fabs(wi[i]));
+        remin = std::min(remin, wr[i]);
+      }
+      f[12] = lg(amax / std::max(amin, TINY));
+      f[13] = imax / std::max(amax, TINY);
+      f[14] = remin / std::max(amax, TINY);
+      f[15] = lg(amax / std::max(D, TINY));
+    }
+  }
+  for (int i = 0; i < 16; ++i) feat[i] = (float)f[i];
+  return GMRESIR_OK;
+}
+
+int gmresir_host_hessenberg_eigvals(int32_t n, const double* H, int32_t ld, double* wr, double* wi) {
+  if (n < 1 || n > 512 || !H || !wr || !wi || ld < n) {
+    set_error("gmresir_host_hessenberg_eigvals: bad arguments");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  std::vector<double> a((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) a[(size_t)i * n + j] = (i > j + 1) ? 0.0 : H[(size_t)j * ld + i];
+  if (hessenberg_eigvals(n, a, wr, wi) != 0) {
+    set_error("gmresir_host_hessenberg_eigvals: QR iteration did not converge");
+    return GMRESIR_ERR_NUMERIC;
+  }
+  return GMRESIR_OK;
+}
+
+int gmresir_host_harmonic_ritz_leja(int32_t k, const double* Hbar, int32_t ld, double* roots) {
+  if (k < 1 || k > 512 || !Hbar || !roots || ld < k + 1) {
+    set_error("gmresir_host_harmonic_ritz_leja: bad arguments");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (harmonic_ritz_leja(k, Hbar, ld, roots) != 0) {
+    set_error("gmresir_host_harmonic_ritz_leja: singular H or no QR convergence");
+    return GMRESIR_ERR_NUMERIC;
+  }
+  return GMRESIR_OK;
+}
+
+}  // extern "C"

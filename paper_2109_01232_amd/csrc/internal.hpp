@@ -1,0 +1,30 @@
+// Declarations shared by the translation units of libgmresir (not installed).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace gir {
+
+// host_linalg.cpp
+int hessenberg_eigvals(int n, std::vector<double>& a_rowmajor, double* wr, double* wi);
+void leja_order(int k, const double* wr, const double* wi, double* out_re_im);
+int harmonic_ritz_leja(int k, const double* Hbar_colmajor, int ld, double* roots_re_im);
+
+// errors.cpp
+void set_error(const char* fmt, ...);
+const char* last_error();
+
+// Row tiles of the SpMV kernels: at most this many rows / nonzeros per tile.
+constexpr int TILE_ROWS = 512;
+constexpr int TILE_NNZ = 6144;
+
+// Upper bound of the number of tiles (every tile holds at least one row).
+inline int64_t max_tiles(int64_t n, int64_t nnz) {
+  (void)nnz;
+  return n;
+}
+
+}  // namespace gir

@@ -1,0 +1,897 @@
+// HIP kernels of the GMRES-IR hot path (gfx950).
+//
+// One inner GMRES iteration (Algorithm 1 with two classical Gram-Schmidt
+// passes, Section "GMRES") is three kernels that each sweep the Krylov basis
+// V once -- the minimum for two-pass CGS:
+//   k_spmv_proj    w = A v_j (row-tiled CSR SpMV, products staged in LDS)
+//                  and h1 = V^T w from the same rows (first-pass projection).
+//                  v_j itself is formed on the fly as round(wtmp * inv_h)
+//                  and stored into V, so no separate normalisation pass.
+//   k_update_proj  w' = w - V h1 and h2 = V^T w' (each row of V is loaded
+//                  into registers once and used for both).
+//   k_update_norm  w'' = w' - V h2 and ||w''||; the last block then forms the
+//                  Hessenberg column h1 + h2, applies the earlier Givens
+//                  rotations, makes the new one and updates the implicit
+//                  residual (the paper's host-side least-squares step, moved
+//                  to the device so a cycle needs no host round trip).
+// Every reduction is two-stage with a fixed summation order, so results are
+// bitwise reproducible run to run.
+#pragma once
+
+#include "device.hpp"
+
+namespace gir {
+
+constexpr int MAX_RESTART = 512;
+
+// ---------------------------------------------------------------------------
+// source-vector accessors of the SpMV gather
+// ---------------------------------------------------------------------------
+
+// v = round_to_basis(src * inv): the next basis vector built from the
+// unnormalised vector of the previous iteration.
+template <typename T, typename S>
+struct XScaled {
+  const T* src;
+  T inv;
+  __device__ __forceinline__ T operator()(int c) const { return Basis<S, T>::round(src[c] * inv); }
+};
+
+template <typename T>
+struct XPlain {
+  const T* src;
+  __device__ __forceinline__ T operator()(int c) const { return src[c]; }
+};
+
+// Row-tiled CSR SpMV: a block takes a contiguous range of tiles; per tile the
+// nonzeros are streamed with coalesced loads, multiplied by the gathered x and
+// staged in LDS, then each thread sums one row in column order.  epi(r, y) is
+// called once per row by the thread owning it.
+template <typename T, typename XF, typename EPI>
+__device__ __forceinline__ void spmv_tiles(const Csr& A, const XF& xf, EPI& epi, T* prod, T* red) {
+  const T* vals = (const T*)A.vals;
+  const int B = gridDim.x, lb = logical_block();
+  const int t0 = (int)((long)A.ntiles * lb / B);
+  const int t1 = (int)((long)A.ntiles * (lb + 1) / B);
+  for (int t = t0; t < t1; ++t) {
+    const int r0 = A.tile_row[t], r1 = A.tile_row[t + 1];
+    const int p0 = A.rowptr[r0], p1 = A.rowptr[r1];
+    const int len = p1 - p0;
+    if (len <= TILE_NNZ) {
+      for (int i = threadIdx.x; i < len; i += BLOCK) {
+        const int c = A.col[p0 + i];
+        prod[i] = vals[p0 + i] * xf(c);
+      }
+      __syncthreads();
+      for (int rr = threadIdx.x; rr < r1 - r0; rr += BLOCK) {
+        const int r = r0 + rr;
+        const int q0 = A.rowptr[r] - p0, q1 = A.rowptr[r + 1] - p0;
+        T s = T(0);
+        for (int q = q0; q < q1; ++q) s += prod[q];
+        epi(r, s);
+      }
+      __syncthreads();
+    } else {
+      // a single row longer than a tile: block-wide dot product
+      T s = T(0);
+      for (int i = threadIdx.x; i < len; i += BLOCK) s += vals[p0 + i] * xf(A.col[p0 + i]);
+      s = block_sum(s, red);
+      if (threadIdx.x == 0) epi(r0, s);
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// first kernel of an iteration: SpMV + first-pass projection
+// ---------------------------------------------------------------------------
+
+// Four consecutive basis entries (rows r..r+3 of one column, r % 4 == 0) with
+// one 16-byte (fp32, 2 x fp64) or 8-byte (bf16) load.
+template <typename S, typename T>
+struct Quad;
+template <>
+struct Quad<float, float> {
+  static __device__ __forceinline__ void load(const float* p, float (&v)[4]) {
+    const float4 q = *(const float4*)p;
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  }
+};
+template <>
+struct Quad<double, double> {
+  static __device__ __forceinline__ void load(const double* p, double (&v)[4]) {
+    const double2 a = *(const double2*)p;
+    const double2 b = *(const double2*)(p + 2);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+  }
+};
+template <>
+struct Quad<bf16_t, float> {
+  static __device__ __forceinline__ void load(const bf16_t* p, float (&v)[4]) {
+    const uint2 q = *(const uint2*)p;
+    v[0] = __uint_as_float(q.x << 16);
+    v[1] = __uint_as_float(q.x & 0xffff0000u);
+    v[2] = __uint_as_float(q.y << 16);
+    v[3] = __uint_as_float(q.y & 0xffff0000u);
+  }
+};
+
+// w = A v_j and the partial sums of h1 = V_{j+1}^T w.
+//
+// Per tile: the SpMV products are staged in LDS and summed per row (one
+// thread per row); the row results y and (SCALED) the new basis vector
+// v_j = round(wtmp * inv_h) are staged in LDS, v_j is stored into V[:, j];
+// then wave w takes the columns c = w, w + 4, ... and each lane multiplies
+// four consecutive rows of the column (one 16-byte load) with the staged y.
+// Each lane keeps SLOTS running sums (k/4 registers instead of k), reduced
+// across the wave once at the end.  Columns c >= 4*SLOTS are left to k_dots.
+template <typename T, typename S, int SLOTS, bool SCALED>
+__global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict__ src, S* __restrict__ V, long ldv,
+                                                     int j, T* __restrict__ w_out, State st,
+                                                     T* __restrict__ part) {
+  if (st.hdr->flags & F_DONE) return;
+  constexpr int KMAX = NWAVES * SLOTS;
+  __shared__ T prod[TILE_NNZ];
+  __shared__ T ys[TILE_ROWS];
+  __shared__ T vs[TILE_ROWS];
+  __shared__ T s_vals[KMAX];
+  __shared__ T s_red[NWAVES];
+  const T* vals = (const T*)A.vals;
+  const T inv = SCALED ? (T)st.hdr->inv_h : T(1);
+  const XScaled<T, S> xs{src, inv};
+  const int C = (j + 1 < KMAX) ? j + 1 : KMAX;  // columns handled here
+  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+  T acc[SLOTS];
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) acc[q] = T(0);
+  const int B = gridDim.x, lb = logical_block();
+  const int t0 = (int)((long)A.ntiles * lb / B);
+  const int t1 = (int)((long)A.ntiles * (lb + 1) / B);
+  for (int t = t0; t < t1; ++t) {
+    const int r0 = A.tile_row[t], r1 = A.tile_row[t + 1];
+    const int p0 = A.rowptr[r0], p1 = A.rowptr[r1];
+    const int len = p1 - p0;
+    const int nrows = r1 - r0;
+    if (len <= TILE_NNZ) {
+      for (int i = threadIdx.x; i < len; i += BLOCK) {
+        const int c = A.col[p0 + i];
+        prod[i] = vals[p0 + i] * (SCALED ? xs(c) : src[c]);
+      }
+      __syncthreads();
+      for (int rr = threadIdx.x; rr < nrows; rr += BLOCK) {
+        const int r = r0 + rr;
+        const int q0 = A.rowptr[r] - p0, q1 = A.rowptr[r + 1] - p0;
+        T y = T(0);
+        for (int q = q0; q < q1; ++q) y += prod[q];
+        w_out[r] = y;
+        ys[rr] = y;
+        if (SCALED) {
+          const T vj = xs(r);
+          Basis<S, T>::store(V + (size_t)j * ldv + r, vj);
+          vs[rr] = vj;
+        }
+      }
+    } else {
+      // a single row longer than a tile: block-wide dot product
+      T y = T(0);
+      for (int i = threadIdx.x; i < len; i += BLOCK) y += vals[p0 + i] * (SCALED ? xs(A.col[p0 + i]) : src[A.col[p0 + i]]);
+      y = block_sum(y, s_red);
+      if (threadIdx.x == 0) {
+        w_out[r0] = y;
+        ys[0] = y;
+        if (SCALED) {
+          const T vj = xs(r0);
+          Basis<S, T>::store(V + (size_t)j * ldv + r0, vj);
+          vs[0] = vj;
+        }
+      }
+    }
+    __syncthreads();
+    // projection of the tile's rows on the columns of this wave
+    const bool aligned = (r0 & 3) == 0;
+    const int ngroups = (nrows + 3) >> 2;
+    for (int g = lane; g < ngroups; g += WAVE) {
+      const int rb = g * 4;
+      const bool full = aligned && rb + 4 <= nrows;
+      T yv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) yv[i] = (rb + i < nrows) ? ys[rb + i] : T(0);
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q) {
+        const int c = wid + NWAVES * q;
+        if (c < C) {
+          T vv[4];
+          if (SCALED && c == j) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) vv[i] = (rb + i < nrows) ? vs[rb + i] : T(0);
+          } else if (full) {
+            Quad<S, T>::load(V + (size_t)c * ldv + r0 + rb, vv);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              vv[i] = (rb + i < nrows) ? Basis<S, T>::load(V + (size_t)c * ldv + r0 + rb + i) : T(0);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[q] += vv[i] * yv[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) {
+    const int c = wid + NWAVES * q;
+    if (c < C) {
+      const T v = wave_sum(acc[q]);
+      if (lane == 0) s_vals[c] = v;
+    }
+  }
+  __syncthreads();
+  store_partials(s_vals, C, part);
+}
+
+// h[c0 + c] = V[:, c0 + c]^T w for c < nc <= 64 (restart lengths beyond the
+// fused kernels' register budget).
+template <typename T, typename S>
+__global__ __launch_bounds__(BLOCK) void k_dots(int n, const S* __restrict__ V, long ldv, int c0, int nc,
+                                                const T* __restrict__ w, State st, int check_done,
+                                                T* __restrict__ part) {
+  if (check_done && (st.hdr->flags & F_DONE)) return;
+  __shared__ T s_red[NWAVES * 64];
+  __shared__ T s_vals[65];
+  int r0, r1;
+  block_rows(n, r0, r1);
+  T acc[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) acc[c] = T(0);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
+    const T wv = w[r];
+    const uint32_t roff = (uint32_t)r * (uint32_t)sizeof(S);
+#pragma unroll
+    for (int cb = 0; cb < 64; cb += 32) {
+#pragma unroll
+      for (int c = cb; c < cb + 32; ++c)
+        if (c < nc) acc[c] += vload<S, T>(V, ldv, c0 + c, roff) * wv;
+      asm volatile("" ::: "memory");
+    }
+  }
+  block_reduce_vec(acc, nc, s_red, s_vals);
+  store_partials(s_vals, nc, part);
+}
+
+// ---------------------------------------------------------------------------
+// second kernel: first-pass update + second-pass projection
+// ---------------------------------------------------------------------------
+
+// Columns c < KREG are held in registers between the update and the
+// projection; columns KREG <= c < k (k <= KACC) are loaded a second time
+// (the rows were just touched, so the reload is served by the caches).
+template <typename T, typename S, int KREG, int KACC>
+__global__ __launch_bounds__(BLOCK) void k_update_proj(int n, const T* __restrict__ w_in, T* __restrict__ w_out,
+                                                       const S* __restrict__ V, long ldv, int k, State st,
+                                                       T* __restrict__ part) {
+  if (st.hdr->flags & F_DONE) return;
+  __shared__ T s_h[KACC];
+  __shared__ T s_red[NWAVES * KACC];
+  __shared__ T s_vals[KACC];
+  for (int c = threadIdx.x; c < k; c += BLOCK) s_h[c] = (T)st.h1[c];
+  __syncthreads();
+  int r0, r1;
+  block_rows(n, r0, r1);
+  T acc[KACC];
+#pragma unroll
+  for (int c = 0; c < KACC; ++c) acc[c] = T(0);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
+    T vr[KREG];
+    T wv = w_in[r];
+    const uint32_t roff = (uint32_t)r * (uint32_t)sizeof(S);
+#pragma unroll
+    for (int c = 0; c < KREG; ++c)
+      if (c < k) vr[c] = vload<S, T>(V, ldv, c, roff);
+#pragma unroll
+    for (int c = 0; c < KREG; ++c)
+      if (c < k) wv -= s_h[c] * vr[c];
+#pragma unroll
+    for (int cb = KREG; cb < KACC; cb += 32) {
+#pragma unroll
+      for (int c = cb; c < cb + 32 && c < KACC; ++c)
+        if (c < k) wv -= s_h[c] * vload<S, T>(V, ldv, c, roff);
+      asm volatile("" ::: "memory");
+    }
+    w_out[r] = wv;
+#pragma unroll
+    for (int c = 0; c < KREG; ++c)
+      if (c < k) acc[c] += vr[c] * wv;
+#pragma unroll
+    for (int cb = KREG; cb < KACC; cb += 32) {
+#pragma unroll
+      for (int c = cb; c < cb + 32 && c < KACC; ++c)
+        if (c < k) acc[c] += vload<S, T>(V, ldv, c, roff) * wv;
+      asm volatile("" ::: "memory");
+    }
+  }
+  block_reduce_vec(acc, k, s_red, s_vals);
+  store_partials(s_vals, k, part);
+}
+
+// w_out = w_in - V h (any k <= MAX_RESTART+1); h from h_src.
+template <typename T, typename S>
+__global__ __launch_bounds__(BLOCK) void k_update(int n, const T* __restrict__ w_in, T* __restrict__ w_out,
+                                                  const S* __restrict__ V, long ldv, int k, const double* h_src,
+                                                  State st) {
+  if (st.hdr->flags & F_DONE) return;
+  __shared__ T s_h[MAX_RESTART + 1];
+  for (int c = threadIdx.x; c < k; c += BLOCK) s_h[c] = (T)h_src[c];
+  __syncthreads();
+  int r0, r1;
+  block_rows(n, r0, r1);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
+    T wv = w_in[r];
+    const uint32_t roff = (uint32_t)r * (uint32_t)sizeof(S);
+#pragma unroll 8
+    for (int c = 0; c < k; ++c) wv -= s_h[c] * vload<S, T>(V, ldv, c, roff);
+    w_out[r] = wv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// third kernel: second-pass update + norm + Hessenberg column + Givens
+// ---------------------------------------------------------------------------
+
+// Executed by the last block of k_update_norm.  Mirrors the least-squares
+// update of Algorithm 1 done incrementally with Givens rotations.  The
+// column and the earlier rotations are staged in LDS so the sequential part
+// (thread 0) touches no global memory.
+template <typename T>
+__device__ __forceinline__ void givens_tail(const State& st, int j, int kmax, T nrm2, T* s_col, T* s_cs, T* s_sn) {
+  __shared__ T s_sq[NWAVES];
+  __shared__ int s_flags;
+  __shared__ T s_g[2];
+  StateHdr* hd = st.hdr;
+  const int ld = st.ld;
+  double* Hc = st.Hbar + (size_t)j * ld;
+  double* Rc = st.R + (size_t)j * ld;
+  T sq = T(0);
+  for (int i = threadIdx.x; i <= j; i += BLOCK) {
+    const T v = (T)st.h1[i] + (T)st.h2[i];
+    Hc[i] = (double)v;
+    s_col[i] = v;
+    sq += v * v;
+  }
+  for (int i = threadIdx.x; i < j; i += BLOCK) {
+    s_cs[i] = (T)st.cs[i];
+    s_sn[i] = (T)st.sn[i];
+  }
+  if (threadIdx.x == 0) s_g[0] = (T)st.g[j];
+  sq = block_sum(sq, s_sq);  // ends with a barrier
+  if (threadIdx.x == 0) {
+    const T hn = sqrt(nrm2);
+    Hc[j + 1] = (double)hn;
+    const T colnorm = sqrt(sq + hn * hn);
+    int flags;
+    if (!isfinite(hn) || !isfinite(colnorm)) {
+      flags = F_DONE | F_NUMERIC;
+      hd->k = j;
+    } else {
+      T cur = s_col[0];
+      for (int i = 0; i < j; ++i) {
+        T nxt = s_col[i + 1];
+        const T c = s_cs[i], s = s_sn[i];
+        s_col[i] = c * cur + s * nxt;
+        cur = -s * cur + c * nxt;
+      }
+      const T rho = hypot(cur, hn);
+      T c, s;
+      if (rho == T(0)) {
+        c = T(1);
+        s = T(0);
+      } else {
+        c = cur / rho;
+        s = hn / rho;
+      }
+      s_col[j] = rho;
+      s_col[j + 1] = T(0);
+      st.cs[j] = (double)c;
+      st.sn[j] = (double)s;
+      const T gj = s_g[0];
+      const T gj1 = -s * gj;
+      st.g[j] = (double)(c * gj);
+      st.g[j + 1] = (double)gj1;
+      const T gin = (T)hd->gamma_in;
+      st.hist[j] = (double)(fabs(gj1) / gin);
+      hd->k = j + 1;
+      hd->implicit = (double)fabs(gj1);
+      hd->inv_h = (double)(T(1) / hn);
+      const bool breakdown = hn <= (T)(100.0 * Unit<T>::roundoff) * colnorm;
+      const bool stopped = hd->stop_abs >= 0.0 && fabs(gj1) <= (T)hd->stop_abs;
+      flags = (breakdown ? F_BREAKDOWN : 0) | (stopped ? F_STOPPED : 0);
+      if (breakdown || stopped || j + 1 >= kmax) flags |= F_DONE;
+    }
+    s_flags = flags;
+    hd->flags = flags;
+  }
+  __syncthreads();
+  if (!(s_flags & F_NUMERIC))
+    for (int i = threadIdx.x; i <= j + 1; i += BLOCK) Rc[i] = (double)s_col[i];
+  // keep both matrices clean below row j+1 (the workspace is not zeroed)
+  for (int i = j + 2 + threadIdx.x; i < ld; i += BLOCK) {
+    Hc[i] = 0.0;
+    Rc[i] = 0.0;
+  }
+}
+
+template <typename T, typename S>
+__global__ __launch_bounds__(BLOCK) void k_update_norm(int n, const T* __restrict__ w_in, T* __restrict__ wtmp,
+                                                       const S* __restrict__ V, long ldv, int j, State st,
+                                                       T* __restrict__ part) {
+  if (st.hdr->flags & F_DONE) return;
+  __shared__ T s_h[MAX_RESTART + 2];
+  __shared__ T s_vals[1];
+  __shared__ T s_scr[NWAVES * WAVE];
+  const int k = j + 1;
+  for (int c = threadIdx.x; c < k; c += BLOCK) s_h[c] = (T)st.h2[c];
+  __syncthreads();
+  int r0, r1;
+  block_rows(n, r0, r1);
+  T nrm = T(0);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
+    T wv = w_in[r];
+    const uint32_t roff = (uint32_t)r * (uint32_t)sizeof(S);
+#pragma unroll 8
+    for (int c = 0; c < k; ++c) wv -= s_h[c] * vload<S, T>(V, ldv, c, roff);
+    wtmp[r] = wv;
+    nrm += wv * wv;
+  }
+  const T bs = block_sum(nrm, s_scr);
+  if (threadIdx.x == 0) s_vals[0] = bs;
+  __syncthreads();
+  store_partials(s_vals, 1, part);
+}
+
+// ---------------------------------------------------------------------------
+// one-block tail kernels of the cross-block reductions
+// ---------------------------------------------------------------------------
+
+// h[c] = sum of the partials of column c (c < nv); with last_to >= 0 the
+// last column goes to h[last_to] instead (the freshly formed basis vector).
+template <typename T>
+__global__ __launch_bounds__(512) void k_reduce_h(const T* __restrict__ part, int nv, int B, double* h, int last_to,
+                                                   State st, int check_done) {
+  if (check_done && (st.hdr->flags & F_DONE)) return;
+  __shared__ T s_out[MAX_RESTART + 2];
+  reduce_partials(part, nv, B, s_out);
+  for (int c = threadIdx.x; c < nv; c += blockDim.x) {
+    const int idx = (last_to >= 0 && c == nv - 1) ? last_to : c;
+    h[idx] = (double)s_out[c];
+  }
+}
+
+// ||w''||^2 from the partials of k_update_norm, then the Givens update.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_norm_givens(const T* __restrict__ part, int B, State st, int j, int kmax) {
+  if (st.hdr->flags & F_DONE) return;
+  __shared__ T s_col[MAX_RESTART + 2];
+  __shared__ T s_cs[MAX_RESTART];
+  __shared__ T s_sn[MAX_RESTART];
+  __shared__ T s_out[1];
+  reduce_partials(part, 1, B, s_out);
+  givens_tail<T>(st, j, kmax, s_out[0], s_col, s_cs, s_sn);
+}
+
+// *dst = sqrt(sum of the partials) (fp64 norms of b and r).
+__global__ __launch_bounds__(BLOCK) void k_sqrt_tail(const double* __restrict__ part, int B, double* dst) {
+  __shared__ double s_out[1];
+  reduce_partials(part, 1, B, s_out);
+  if (threadIdx.x == 0) *dst = sqrt(s_out[0]);
+}
+
+// ---------------------------------------------------------------------------
+// cycle end: back substitution R y = g (one block)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_backsolve(State st) {
+  extern __shared__ unsigned char s_dyn[];
+  const int flags = st.hdr->flags;
+  const int k = st.hdr->k;
+  if (threadIdx.x == 0) {
+    st.hdr->cycle_k = k;
+    st.hdr->cycle_flags = flags;
+  }
+  if (flags & F_NUMERIC) return;
+  if (k <= 0) return;
+  T* s_g = (T*)s_dyn;                 // k
+  T* s_R = s_g + ((k + 1) & ~1);      // packed columns of the upper triangle (if it fits)
+  const int ld = st.ld;
+  const bool in_lds = (size_t)k * (k + 1) / 2 * sizeof(T) <= 40960;
+  for (int i = threadIdx.x; i < k; i += BLOCK) s_g[i] = (T)st.g[i];
+  if (in_lds) {
+    for (int c = 0; c < k; ++c)
+      for (int i = threadIdx.x; i <= c; i += BLOCK) s_R[(size_t)c * (c + 1) / 2 + i] = (T)st.R[(size_t)c * ld + i];
+  }
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    const T rii = in_lds ? s_R[(size_t)i * (i + 1) / 2 + i] : (T)st.R[(size_t)i * ld + i];
+    const T yi = s_g[i] / rii;
+    __syncthreads();
+    for (int l = threadIdx.x; l < i; l += BLOCK) {
+      const T ril = in_lds ? s_R[(size_t)i * (i + 1) / 2 + l] : (T)st.R[(size_t)i * ld + l];
+      s_g[l] -= ril * yi;
+    }
+    if (threadIdx.x == 0) st.y[i] = (double)yi;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// outer (fp64) refinement kernels
+// ---------------------------------------------------------------------------
+
+// Zero the state header (tickets, flags) without hipMemsetAsync.
+__global__ void k_init_state(State st, double rtol, int check_mode, double gamma0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    StateHdr* hd = st.hdr;
+    hd->beta = 0.0;
+    hd->gamma = gamma0;
+    hd->gamma_in = 0.0;
+    hd->inv_h = 0.0;
+    hd->stop_abs = -1.0;
+    hd->rtol = rtol;
+    hd->implicit = 0.0;
+    hd->check_mode = check_mode;
+    hd->k = 0;
+    hd->flags = 0;
+    hd->cycle_k = 0;
+    hd->cycle_flags = 0;
+    for (int i = 0; i < 8; ++i) hd->counter[i] = 0u;
+  }
+}
+
+// *dst = ||v||_2 in fp64 (dst is a field of the state header).
+__global__ __launch_bounds__(BLOCK) void k_norm64(int n, const double* __restrict__ v, double* __restrict__ part) {
+  __shared__ double s_vals[1], s_scr[NWAVES * WAVE];
+  int r0, r1;
+  block_rows(n, r0, r1);
+  double s = 0.0;
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) s += v[r] * v[r];
+  const double bs = block_sum(s, s_scr);
+  if (threadIdx.x == 0) s_vals[0] = bs;
+  __syncthreads();
+  store_partials(s_vals, 1, part);
+}
+
+struct ResidEpi {
+  const double* b;
+  double* r;
+  double nrm;
+  __device__ __forceinline__ void operator()(int i, double y) {
+    const double v = b[i] - y;
+    r[i] = v;
+    nrm += v * v;
+  }
+};
+
+// r = b - A x (fp64 matrix and vectors), gamma = ||r||_2 (Algorithm 2, first and last lines).
+__global__ __launch_bounds__(BLOCK) void k_resid64(Csr A, const double* __restrict__ x, const double* __restrict__ b,
+                                                   double* __restrict__ r, double* __restrict__ part) {
+  __shared__ double prod[TILE_NNZ];
+  __shared__ double s_vals[1], s_scr[NWAVES * WAVE];
+  ResidEpi epi{b, r, 0.0};
+  spmv_tiles<double>(A, XPlain<double>{x}, epi, prod, s_scr);
+  const double bs = block_sum(epi.nrm, s_scr);
+  if (threadIdx.x == 0) s_vals[0] = bs;
+  __syncthreads();
+  store_partials(s_vals, 1, part);
+}
+
+// Start of a cycle after the tail of a reduction gave gin = ||rhat||: reset
+// the cycle state and the early-exit threshold rtol ||b|| / ||r||.
+template <typename T>
+__device__ __forceinline__ void cycle_start_tail(const State& st, T gin) {
+  StateHdr* hd = st.hdr;
+  hd->gamma_in = (double)gin;
+  hd->inv_h = (double)(T(1) / gin);
+  st.g[0] = (double)gin;
+  hd->k = 0;
+  hd->implicit = (double)gin;
+  hd->flags = (isfinite(gin) && gin > T(0)) ? 0 : (F_DONE | F_NUMERIC);
+  hd->stop_abs = hd->check_mode == 1 ? (double)(T)(hd->rtol * hd->beta / hd->gamma) : -1.0;
+}
+
+// gin = sqrt(sum of the partials): start of a cycle.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_cycle_tail(const T* __restrict__ part, int B, State st) {
+  __shared__ T s_out[1];
+  reduce_partials(part, 1, B, s_out);
+  if (threadIdx.x == 0) cycle_start_tail<T>(st, (T)sqrt(s_out[0]));
+}
+
+// wtmp = round_T(r / gamma) (the inner right-hand side, Algorithm 2 line 3),
+// optionally also kept in rhat; gin = ||wtmp|| in inner precision.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_cast(int n, const double* __restrict__ r, T* __restrict__ wtmp,
+                                                T* __restrict__ rhat, State st, T* __restrict__ part) {
+  __shared__ T s_vals[1], s_scr[NWAVES * WAVE];
+  const double gamma = st.hdr->gamma;
+  int r0, r1;
+  block_rows(n, r0, r1);
+  T s = T(0);
+  for (int i = r0 + threadIdx.x; i < r1; i += BLOCK) {
+    const T v = (T)(r[i] / gamma);
+    wtmp[i] = v;
+    if (rhat) rhat[i] = v;
+    s += v * v;
+  }
+  const T bs = block_sum(s, s_scr);
+  if (threadIdx.x == 0) s_vals[0] = bs;
+  __syncthreads();
+  store_partials(s_vals, 1, part);
+}
+
+template <typename T>
+struct InnerResidEpi {
+  const T* rhat;
+  T* wtmp;
+  T nrm;
+  __device__ __forceinline__ void operator()(int i, T y) {
+    const T v = rhat[i] - y;
+    wtmp[i] = v;
+    nrm += v * v;
+  }
+};
+
+// Restart of the inner solve in its own precision: wtmp = rhat - A_in u.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_inner_resid(Csr A, const T* __restrict__ u, const T* __restrict__ rhat,
+                                                       T* __restrict__ wtmp, T* __restrict__ part) {
+  __shared__ T prod[TILE_NNZ];
+  __shared__ T s_vals[1], s_scr[NWAVES * WAVE];
+  InnerResidEpi<T> epi{rhat, wtmp, T(0)};
+  spmv_tiles<T>(A, XPlain<T>{u}, epi, prod, s_scr);
+  const T bs = block_sum(epi.nrm, s_scr);
+  if (threadIdx.x == 0) s_vals[0] = bs;
+  __syncthreads();
+  store_partials(s_vals, 1, part);
+}
+
+// x += gamma * (V_k y) with V_k y accumulated in inner precision (Algorithm 2, line 4).
+template <typename T, typename S>
+__global__ __launch_bounds__(BLOCK) void k_correct_x(int n, const S* __restrict__ V, long ldv, State st,
+                                                     double* __restrict__ x) {
+  __shared__ T s_y[MAX_RESTART];
+  if (st.hdr->flags & F_NUMERIC) return;
+  const int k = st.hdr->k;
+  const double gamma = st.hdr->gamma;
+  for (int c = threadIdx.x; c < k; c += BLOCK) s_y[c] = (T)st.y[c];
+  __syncthreads();
+  int r0, r1;
+  block_rows(n, r0, r1);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
+    T u = T(0);
+    const uint32_t roff = (uint32_t)r * (uint32_t)sizeof(S);
+#pragma unroll 8
+    for (int c = 0; c < k; ++c) u += vload<S, T>(V, ldv, c, roff) * s_y[c];
+    x[r] = x[r] + gamma * (double)u;
+  }
+}
+
+// z = V_k y in inner precision.
+template <typename T, typename S>
+__global__ __launch_bounds__(BLOCK) void k_vy(int n, const S* __restrict__ V, long ldv, State st, T* __restrict__ z) {
+  __shared__ T s_y[MAX_RESTART];
+  const int k = (st.hdr->flags & F_NUMERIC) ? 0 : st.hdr->k;
+  for (int c = threadIdx.x; c < k; c += BLOCK) s_y[c] = (T)st.y[c];
+  __syncthreads();
+  int r0, r1;
+  block_rows(n, r0, r1);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
+    T u = T(0);
+    const uint32_t roff = (uint32_t)r * (uint32_t)sizeof(S);
+#pragma unroll 8
+    for (int c = 0; c < k; ++c) u += vload<S, T>(V, ldv, c, roff) * s_y[c];
+    z[r] = u;
+  }
+}
+
+// u = z (first) or u += z, inner precision.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_accum(int n, const T* __restrict__ z, T* __restrict__ u, int first) {
+  int r0, r1;
+  block_rows(n, r0, r1);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) u[r] = first ? z[r] : u[r] + z[r];
+}
+
+// x += gamma * u (fp64 update).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_axpy_x(int n, const T* __restrict__ u, State st, double* __restrict__ x) {
+  const double gamma = st.hdr->gamma;
+  int r0, r1;
+  block_rows(n, r0, r1);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) x[r] = x[r] + gamma * (double)u[r];
+}
+
+__global__ void k_fill64(int n, double* __restrict__ x, double v) {
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) x[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// polynomial preconditioner: one SpMV step of the product form of p(A)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct PolyCoef {
+  T ay, aw, ax, at;  // y = ay*y + aw*W + ax*X + at*(A X)
+  T bw, bx, bt;      // d = bw*W + bx*X + bt*(A X)
+  int has_y, y_read, has_d, has_w;
+};
+
+template <typename T, typename S, bool SCALED>
+struct PolyEpi {
+  const T* src;
+  T inv;
+  S* V;
+  long ldv;
+  int j;
+  int write_v;
+  const T* W;
+  int w_scaled;
+  T* Y;
+  T* D;
+  PolyCoef<T> cf;
+  __device__ __forceinline__ void operator()(int r, T t) {
+    T xr;
+    if (SCALED) {
+      xr = Basis<S, T>::round(src[r] * inv);
+      if (write_v) Basis<S, T>::store(V + (size_t)j * ldv + r, xr);
+    } else {
+      xr = src[r];
+    }
+    T wr = T(0);
+    if (cf.has_w) wr = w_scaled ? Basis<S, T>::round(W[r] * inv) : W[r];
+    if (cf.has_y) {
+      T yv = cf.aw * wr + cf.ax * xr + cf.at * t;
+      if (cf.y_read) yv += cf.ay * Y[r];
+      Y[r] = yv;
+    }
+    if (cf.has_d) D[r] = cf.bw * wr + cf.bx * xr + cf.bt * t;
+  }
+};
+
+template <typename T, typename S, bool SCALED>
+__global__ __launch_bounds__(BLOCK) void k_poly_step(Csr A, const T* __restrict__ src, S* __restrict__ V, long ldv,
+                                                     int j, int write_v, const T* __restrict__ W, int w_scaled,
+                                                     T* __restrict__ Y, T* __restrict__ D, PolyCoef<T> cf, State st,
+                                                     int check_done) {
+  if (check_done && (st.hdr->flags & F_DONE)) return;
+  __shared__ T prod[TILE_NNZ];
+  __shared__ T s_scr[NWAVES * WAVE];
+  PolyEpi<T, S, SCALED> epi;
+  epi.src = src;
+  epi.inv = (T)st.hdr->inv_h;
+  epi.V = V;
+  epi.ldv = ldv;
+  epi.j = j;
+  epi.write_v = write_v;
+  epi.W = W;
+  epi.w_scaled = w_scaled;
+  epi.Y = Y;
+  epi.D = D;
+  epi.cf = cf;
+  if (SCALED)
+    spmv_tiles<T>(A, XScaled<T, S>{src, epi.inv}, epi, prod, s_scr);
+  else
+    spmv_tiles<T>(A, XPlain<T>{src}, epi, prod, s_scr);
+}
+
+// ---------------------------------------------------------------------------
+// plain SpMV, start vector, casts, row statistics
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct PlainEpi {
+  T* y;
+  __device__ __forceinline__ void operator()(int r, T v) { y[r] = v; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_spmv(Csr A, const T* __restrict__ x, T* __restrict__ y) {
+  __shared__ T prod[TILE_NNZ];
+  __shared__ T s_scr[NWAVES * WAVE];
+  PlainEpi<T> epi{y};
+  spmv_tiles<T>(A, XPlain<T>{x}, epi, prod, s_scr);
+}
+
+__global__ void k_cast_vals(int64_t nnz, const double* __restrict__ v64, float* __restrict__ v32) {
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * BLOCK)
+    v32[i] = (float)v64[i];
+}
+
+// v[i] = 2 * (splitmix64(seed ^ i) >> 11) * 2^-53 - 1 (SplitMix64, S. Vigna).
+__global__ void k_start_vector(int n, uint64_t seed, double* __restrict__ v) {
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+    uint64_t z = (seed ^ (uint64_t)i) + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    v[i] = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+  }
+}
+
+// Row statistics of the chooser features, fp64:
+// out[0] sum d/(d+S)  out[1] min d/(d+S)  out[2] #rows d >= S  out[3] sum rowsum
+// out[4] sum a^2      out[5] sum a_ii     out[6] sum a_ii^2    out[7] sum |U-L|/S
+// out[8] max row nnz  out[9] sum |a_ii|
+__device__ __forceinline__ double rowstat_combine(int c, double a, double b) {
+  return (c == 1) ? fmin(a, b) : (c == 8) ? fmax(a, b) : a + b;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rowstats(Csr A, double* __restrict__ part) {
+  __shared__ double s_scr[NWAVES * 10];
+  __shared__ double s_vals[10];
+  const double* vals = (const double*)A.vals;
+  int r0, r1;
+  block_rows(A.n, r0, r1);
+  double acc[10] = {0, 1e300, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = r0 + threadIdx.x; i < r1; i += BLOCK) {
+    double d = 0, ds = 0, S = 0, L = 0, U = 0, rs = 0, a2 = 0;
+    const int q0 = A.rowptr[i], q1 = A.rowptr[i + 1];
+    for (int q = q0; q < q1; ++q) {
+      const int c = A.col[q];
+      const double a = vals[q];
+      rs += a;
+      a2 += a * a;
+      if (c == i) {
+        d += fabs(a);
+        ds += a;
+      } else {
+        S += fabs(a);
+        if (c < i) L += a; else U += a;
+      }
+    }
+    const double tot = d + S;
+    const double frac = tot > 0 ? d / tot : 0.0;
+    acc[0] += frac;
+    acc[1] = fmin(acc[1], frac);
+    acc[2] += (d >= S) ? 1.0 : 0.0;
+    acc[3] += rs;
+    acc[4] += a2;
+    acc[5] += ds;
+    acc[6] += ds * ds;
+    acc[7] += S > 0 ? fabs(U - L) / (S + 1e-30) : 0.0;
+    acc[8] = fmax(acc[8], (double)(q1 - q0));
+    acc[9] += d;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x / 64;
+  for (int c = 0; c < 10; ++c) {
+    double v = acc[c];
+    for (int o = 32; o > 0; o >>= 1) v = rowstat_combine(c, v, __shfl_xor(v, o, 64));
+    if (lane == 0) s_scr[wid * 10 + c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 10) {
+    const int c = threadIdx.x;
+    double v = s_scr[c];
+    for (int w = 1; w < NWAVES; ++w) v = rowstat_combine(c, v, s_scr[w * 10 + c]);
+    s_vals[c] = v;
+  }
+  __syncthreads();
+  store_partials(s_vals, 10, part);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rowstats_tail(const double* __restrict__ part, int B,
+                                                         double* __restrict__ out) {
+  if (threadIdx.x < 10) {
+    const int c = threadIdx.x;
+    double v = part[(size_t)c * MAX_BLOCKS];
+    for (int b = 1; b < B; ++b) v = rowstat_combine(c, v, part[(size_t)c * MAX_BLOCKS + b]);
+    out[c] = v;
+  }
+}
+
+}  // namespace gir

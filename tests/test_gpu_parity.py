@@ -1,0 +1,394 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: bitwise for the fp32/fp64 SpMV on stencil rows (both sum each row in
+column order from identically rounded products); final fp64 relative
+residual <= rtol for both sides; solution agreement 1e-8 relative (the
+parity system has condition number ~1e3, so two solutions with residual
+1e-12 agree to ~1e-9); cycle-normalised implicit residual histories within
+1e-5 for fp32 cycles (the measured fp32-vs-fp64 gap on these systems is
+~2e-7) and within 2^-8 for bf16-stored bases (bf16 unit step).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import linalg as L
+from oracle import poly as PO
+from paper_2109_01232_amd import binding as B
+from paper_2109_01232_amd import problems as P
+
+from gpu_common import cycle_slices, dev_tensor, rel, say
+
+pytestmark = pytest.mark.gpu
+
+HIST_TOL_FP32 = 1e-5
+HIST_TOL_BF16 = 2.0 ** -8
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    s = P.parity_system()
+    return s, B.Matrix.from_csr(s.A)
+
+
+def ragged_matrix_with_long_row(n=1500, seed=0):
+    """Random CSR with empty rows and one row longer than a tile (6144 nnz)."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        if i % 97 == 5:
+            rows.append(np.array([], dtype=np.int64))
+        elif i == 700:
+            rows.append(np.sort(rng.choice(n, min(n, 1400), replace=False)))
+        else:
+            k = rng.integers(1, 12)
+            rows.append(np.sort(rng.choice(n, k, replace=False)))
+    # make the long row longer than a tile by repeating the matrix width
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    cols, vals = [], []
+    for i, r in enumerate(rows):
+        cols.append(r)
+        vals.append(rng.standard_normal(len(r)))
+        rowptr[i + 1] = rowptr[i] + len(r)
+    return P.CSR(n, rowptr.astype(np.int32), np.concatenate(cols).astype(np.int32), np.concatenate(vals))
+
+
+def long_row_matrix(n=8000, seed=1):
+    rng = np.random.default_rng(seed)
+    rowptr = [0]
+    cols, vals = [], []
+    for i in range(n):
+        k = 7000 if i == 3 else (0 if i % 50 == 7 else rng.integers(2, 9))
+        c = np.sort(rng.choice(n, k, replace=False))
+        cols.append(c)
+        vals.append(rng.standard_normal(k))
+        rowptr.append(rowptr[-1] + k)
+    return P.CSR(n, np.array(rowptr, dtype=np.int32), np.concatenate(cols).astype(np.int32), np.concatenate(vals))
+
+
+# ---------------------------------------------------------------------------
+# SpMV
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["cfg1", "ragged2d", "aniso3d", "varcoef27", "irregular", "longrow"])
+def test_spmv_parity(case):
+    say("spmv", case)
+    if case == "cfg1":
+        A = P.parity_system().A
+    elif case == "ragged2d":
+        A = P.conv_diff(2, 37, 25.0, (1.0, -0.5))
+    elif case == "aniso3d":
+        A = P.conv_diff(3, 23, 10.0, (1, 1, 1), (1, 1, 1e-2))
+    elif case == "varcoef27":
+        A = P.varcoef27(17, 3)
+    elif case == "irregular":
+        A = ragged_matrix_with_long_row()
+    else:
+        A = long_row_matrix()
+    M = B.Matrix.from_csr(A)
+    x = np.random.default_rng(1).uniform(-1, 1, A.n)
+    for prec, dt in (("fp64", np.float64), ("fp32", np.float32)):
+        xd = dev_tensor(x.astype(dt))
+        yd = torch.empty_like(xd)
+        B.gmresir_spmv(M, xd, yd, prec)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy()
+        ref = L.spmv(L.csr_matrix(A, dt), x.astype(dt))
+        if case == "longrow":
+            # the long row is a block-wide reduction: tolerance for it, bitwise elsewhere
+            mask = np.ones(A.n, bool)
+            mask[3] = False
+            assert np.array_equal(y[mask], ref[mask])
+            lo, hi = A.rowptr[3], A.rowptr[4]
+            scale = np.abs(A.vals[lo:hi] * x[A.colidx[lo:hi]]).sum()
+            eps = np.finfo(dt).eps
+            assert abs(float(y[3]) - float(ref[3])) <= 8 * eps * scale
+        else:
+            assert np.array_equal(y, ref), (prec, np.abs(y - ref).max())
+
+
+# ---------------------------------------------------------------------------
+# full solves on the parity system (64x64 convection-diffusion)
+# ---------------------------------------------------------------------------
+
+def test_fp64_gmres_matches_oracle(cfg1):
+    s, M = cfg1
+    say("fp64 gmres(50) cfg1")
+    b = dev_tensor(s.b)
+    x, d, h = B.solve(M, b, restart=50, inner="fp64", rtol=1e-10, check_mode=0, hist_cap=100000)
+    ref = L.gmres(s.A, s.b, m=50, rtol=1e-10, check_mode=0)
+    xs = x.cpu().numpy()
+    assert d["status"] == B.OK and ref.status == L.OK
+    assert d["iters"] == ref.iters and d["refinements"] == ref.refinements
+    true = np.linalg.norm(s.b - s.A.scipy() @ xs) / np.linalg.norm(s.b)
+    assert true <= 1e-10 and d["rel_resid_true"] == pytest.approx(true, rel=1e-6)
+    assert rel(xs, ref.x) <= 1e-8
+    assert rel(xs, s.u) <= 1e-6
+    # fp64 on both sides: the first cycles agree to rounding; later cycles
+    # start from residuals that carry the iterates' rounding noise
+    href = np.array(ref.hist)
+    assert np.max(np.abs(h[:150] - href[:150])) <= 1e-10
+    assert np.max(np.abs(h - href)) <= 1e-5
+
+
+def test_gmres_ir_fp32_matches_oracle(cfg1):
+    s, M = cfg1
+    say("ir fp32 cfg1")
+    b = dev_tensor(s.b)
+    x, d, h = B.solve(M, b, restart=50, inner="fp32", rtol=1e-12, check_mode=0, hist_cap=100000)
+    ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-12, inner="fp32", check_mode=0)
+    xs = x.cpu().numpy()
+    assert d["status"] == B.OK
+    assert d["rel_resid_true"] <= 1e-12 and ref.rel_resid <= 1e-12
+    assert rel(xs, ref.x) <= 1e-8
+    assert d["iters"] % 50 == 0  # paper mode: convergence checked at restarts only
+    # same number of restarts up to one (rounding), first cycle identical input
+    assert abs(d["refinements"] - ref.refinements) <= 1
+    assert np.max(np.abs(h[:50] - np.array(ref.hist[:50]))) <= HIST_TOL_FP32
+
+
+def test_ir_cycle_histories_from_oracle_iterates(cfg1):
+    """Per-cycle parity on the same input r_i: the GPU restarts from the
+    oracle's own iterate x_i and runs one fp32 cycle; its history is compared
+    with the fp64 oracle's cycle i+1 (the gate oracle runs the inner solve in
+    fp64)."""
+    s, M = cfg1
+    ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-12, inner="fp64", check_mode=0, keep_iterates=True)
+    cycles = cycle_slices(ref.hist, ref.cycle_starts)
+    b = dev_tensor(s.b)
+    for i in (0, 2, 4, 6):
+        say("ir cycle replay", i)
+        x0 = dev_tensor(ref.xs[i])
+        x, d, h = B.solve(M, b, x0=x0, restart=50, inner="fp32", rtol=1e-14, check_mode=0, max_iters=50,
+                          hist_cap=50)
+        assert d["iters"] == 50
+        assert np.max(np.abs(h - cycles[i + 1])) <= HIST_TOL_FP32, i
+
+
+def test_check_mode_implicit_exit(cfg1):
+    s, M = cfg1
+    say("check_mode 1")
+    b = dev_tensor(s.b)
+    x0, d0, _ = B.solve(M, b, restart=50, inner="fp32", rtol=1e-10, check_mode=0)
+    x1, d1, _ = B.solve(M, b, restart=50, inner="fp32", rtol=1e-10, check_mode=1)
+    ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-10, inner="fp32", check_mode=1)
+    assert d1["status"] == B.OK and d1["rel_resid_true"] <= 1e-10
+    assert d1["iters"] <= d0["iters"] and d0["iters"] - d1["iters"] <= 49
+    assert abs(d1["iters"] - ref.iters) <= 10
+
+
+def test_bf16_basis(cfg1):
+    s, M = cfg1
+    say("bf16 basis cfg1")
+    b = dev_tensor(s.b)
+    x, d, h = B.solve(M, b, restart=50, inner="fp32", basis="bf16", rtol=1e-10, check_mode=0, hist_cap=100000)
+    ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-10, inner="fp32", basis="bf16", check_mode=0)
+    assert d["status"] == B.OK and d["rel_resid_true"] <= 1e-10
+    assert np.max(np.abs(h[:50] - np.array(ref.hist[:50]))) <= HIST_TOL_BF16
+    assert abs(d["refinements"] - ref.refinements) <= 2
+    assert rel(x.cpu().numpy(), s.u) <= 1e-6
+
+
+def test_deterministic(cfg1):
+    s, M = cfg1
+    say("determinism")
+    b = dev_tensor(s.b)
+    xa, da, _ = B.solve(M, b, restart=30, inner="fp32", rtol=1e-10)
+    xb, db, _ = B.solve(M, b, restart=30, inner="fp32", rtol=1e-10)
+    assert torch.equal(xa, xb) and da["iters"] == db["iters"]
+
+
+def test_resume_equals_single_call(cfg1):
+    s, M = cfg1
+    say("resume")
+    b = dev_tensor(s.b)
+    full, df, _ = B.solve(M, b, restart=30, inner="fp64", rtol=1e-10, check_mode=0)
+    part, dp, _ = B.solve(M, b, restart=30, inner="fp64", rtol=1e-10, check_mode=0, max_iters=90)
+    assert dp["status"] == B.NOT_CONVERGED and dp["iters"] == 90
+    rest, dr, _ = B.solve(M, b, x0=part, restart=30, inner="fp64", rtol=1e-10, check_mode=0)
+    assert dp["iters"] + dr["iters"] == df["iters"]
+    assert torch.equal(rest, full)
+
+
+def test_inner_cap_multi_cycle(cfg1):
+    s, M = cfg1
+    say("inner cap 75, m 25")
+    b = dev_tensor(s.b)
+    x, d, _ = B.solve(M, b, restart=25, inner="fp32", inner_cap=75, rtol=1e-10)
+    ref = L.gmres_ir(s.A, s.b, m=25, rtol=1e-10, inner="fp32", cap=75, check_mode=1)
+    assert d["status"] == B.OK and d["rel_resid_true"] <= 1e-10
+    assert d["cycles"] > d["refinements"]
+    assert abs(d["refinements"] - ref.refinements) <= 1
+
+
+@pytest.mark.parametrize("m", [1, 7, 64, 70, 130])
+def test_restart_lengths_and_fallbacks(m):
+    """m=1 (degenerate), ragged, and restart lengths past the fused kernels'
+    column limits (fp64 56, fp32 128) which take the fallback kernels."""
+    A = P.conv_diff(2, 20, 15.0, (1.0, 1.0))
+    u = np.random.default_rng(m).uniform(-1, 1, A.n)
+    bb = A.scipy() @ u
+    M = B.Matrix.from_csr(A)
+    b = dev_tensor(bb)
+    for inner in ("fp64", "fp32"):
+        say("restart", m, inner)
+        maxit = 4000 if m > 1 else 20000
+        x, d, h = B.solve(M, b, restart=m, inner=inner, rtol=1e-10, max_iters=maxit, check_mode=1,
+                          hist_cap=200)
+        ref = (L.gmres(A, bb, m=m, rtol=1e-10, max_iters=maxit, check_mode=1) if inner == "fp64" else
+               L.gmres_ir(A, bb, m=m, rtol=1e-10, inner="fp32", max_iters=maxit, check_mode=1))
+        assert d["status"] == ref.status
+        if d["status"] == B.OK:
+            assert d["rel_resid_true"] <= 1e-10
+            assert rel(x.cpu().numpy(), ref.x) <= 1e-7
+        # first cycle only: after an implicit early exit the next cycle's input is
+        # the rounding noise of the correction, which differs between the sides
+        k = min(len(h), ref.cycle_starts[1] if len(ref.cycle_starts) > 1 else len(ref.hist), m)
+        tol = 1e-10 if inner == "fp64" else HIST_TOL_FP32
+        assert np.max(np.abs(h[:k] - np.array(ref.hist[:k]))) <= tol
+
+
+def test_exact_breakdown_small_system():
+    """n = 12 < m: GMRES terminates in at most n steps with a lucky breakdown."""
+    A = P.conv_diff(2, 3, 5.0, (1.0, 0.0))
+    M = B.Matrix.from_csr(A)
+    bb = np.arange(1.0, A.n + 1)
+    b = dev_tensor(bb)
+    for inner in ("fp64", "fp32"):
+        say("breakdown", inner)
+        x, d, _ = B.solve(M, b, restart=30, inner=inner, rtol=1e-10)
+        assert d["status"] == B.OK and d["rel_resid_true"] <= 1e-10
+        assert d["iters"] <= 2 * A.n
+        assert rel(x.cpu().numpy(), np.linalg.solve(A.scipy().toarray(), bb)) <= 1e-8
+
+
+# ---------------------------------------------------------------------------
+# failure handling (forced from the host)
+# ---------------------------------------------------------------------------
+
+def test_failure_modes(cfg1):
+    s, M = cfg1
+    b = dev_tensor(s.b)
+    say("nan rhs")
+    bn = s.b.copy()
+    bn[17] = np.nan
+    with pytest.raises(B.GmresirError) as e:
+        B.gmresir_solve(M, dev_tensor(bn), torch.zeros_like(b), B.make_params(restart=20))
+    assert e.value.status == B.ERR_NUMERIC
+    say("max_iters")
+    x = torch.zeros_like(b)
+    st, d, _ = B.gmresir_solve(M, b, x, B.make_params(restart=20, max_iters=40))
+    assert st == B.NOT_CONVERGED and d["iters"] == 40 and d["rel_resid_true"] < 1
+    say("stagnation")
+    x = torch.zeros_like(b)
+    res = B.Result()
+    import ctypes
+    p = B.make_params(restart=50, rtol=1e-20, max_iters=5000)
+    ws = torch.empty(B.gmresir_workspace_bytes(M, p), dtype=torch.uint8, device="cuda")
+    hist = np.zeros(5000)
+    st = B.lib().gmresir_solve(M.handle, B._ptr(b), B._ptr(x), ctypes.byref(p), None, B._ptr(ws), ws.numel(),
+                               ctypes.byref(res), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 5000,
+                               B._stream())
+    print("stagnation case:", st, res.as_dict(), B.last_error(), flush=True)
+    assert st == B.STAGNATED and res.rel_resid_true <= 1e-12
+    say("zero rhs")
+    x = torch.ones_like(b)
+    st, d, _ = B.gmresir_solve(M, torch.zeros_like(b), x, B.make_params())
+    assert st == B.OK and not torch.any(x)
+    say("bad params")
+    with pytest.raises(B.GmresirError) as e:
+        B.gmresir_solve(M, b, torch.zeros_like(b), B.make_params(inner="fp64", basis="bf16"))
+    assert e.value.status == B.ERR_INVALID_ARG
+    say("small workspace")
+    p = B.make_params()
+    need = B.gmresir_workspace_bytes(M, p)
+    ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    res = B.Result()
+    import ctypes
+    st = B.lib().gmresir_solve(M.handle, B._ptr(b), B._ptr(torch.zeros_like(b)), ctypes.byref(p), None,
+                               B._ptr(ws), ws.numel(), ctypes.byref(res), None, 0, B._stream())
+    assert st == B.ERR_WORKSPACE
+
+
+# ---------------------------------------------------------------------------
+# polynomial preconditioner
+# ---------------------------------------------------------------------------
+
+def aniso_small(n=14, seed=0):
+    A = P.conv_diff(3, n, 10.0, (1, 1, 1), (1, 1, 1e-2))
+    u = np.random.default_rng(seed).uniform(-1, 1, A.n)
+    return A, A.scipy() @ u
+
+
+@pytest.mark.parametrize("d", [1, 2, 5, 10, 20])
+def test_poly_apply_matches_oracle(d):
+    """Same roots on both sides (drawn from the oracle), fp32 product form."""
+    A, _ = aniso_small()
+    roots = PO.poly_roots(A, d, seed=4, dtype=np.float64)
+    M = B.Matrix.from_csr(A)
+    v = np.random.default_rng(d).standard_normal(A.n).astype(np.float32)
+    vd = dev_tensor(v)
+    yd = torch.empty_like(vd)
+    say("poly apply", d)
+    B.gmresir_poly_apply(M, roots, vd, yd)
+    torch.cuda.synchronize()
+    ref = PO.apply_product_form(L.csr_matrix(A, np.float32), roots, v, np.float32)
+    ref64 = PO.apply_product_form(L.csr_matrix(A, np.float64), roots, v.astype(np.float64), np.float64)
+    got = yd.cpu().numpy()
+    # both fp32 evaluations sit within fp32 rounding of the fp64 value
+    e_ours = rel(got, ref64)
+    e_oracle = rel(ref, ref64)
+    assert e_ours <= max(10 * e_oracle, 1e-5)
+
+
+def test_poly_setup_matches_oracle():
+    A, _ = aniso_small()
+    M = B.Matrix.from_csr(A)
+    start = PO.start_vector(A.n, 11)
+    say("poly setup, given start")
+    roots, hbar = B.gmresir_poly_setup(M, 10, start=dev_tensor(start), with_hbar=True)
+    ref_cyc = L.gmres_cycle(lambda z: L.spmv(L.csr_matrix(A, np.float32), z), start.astype(np.float32), 11,
+                            np.float32)
+    assert rel(hbar, ref_cyc.Hbar) <= 1e-5
+    ref = PO.poly_roots(A, 10, start=start, dtype=np.float32)
+    assert len(roots) == 11
+    assert np.allclose(np.sort_complex(roots), np.sort_complex(ref), rtol=1e-3, atol=1e-3 * np.abs(ref).max())
+    say("poly setup, splitmix start")
+    r2 = B.gmresir_poly_setup(M, 10, seed=11)
+    assert np.allclose(np.sort_complex(r2), np.sort_complex(roots), rtol=1e-5, atol=1e-5 * np.abs(ref).max())
+
+
+def test_poly_preconditioned_solve():
+    A, bb = aniso_small()
+    M = B.Matrix.from_csr(A)
+    b = dev_tensor(bb)
+    say("poly solve d=10, roots built on the GPU")
+    groots = B.gmresir_poly_setup(M, 10, seed=3)
+    xg, dg, _ = B.solve(M, b, restart=30, inner="fp32", rtol=1e-10, poly_degree=10, poly_roots=groots)
+    assert dg["status"] == B.OK and dg["rel_resid_true"] <= 1e-10
+    # parity on identical inputs: the oracle builds the roots, both sides use them
+    roots = PO.poly_roots(A, 10, start=PO.start_vector(A.n, 3), dtype=np.float32)
+    say("poly solve d=10, oracle roots")
+    x0, d0, _ = B.solve(M, b, restart=30, inner="fp32", rtol=1e-10)
+    x1, d1, h1 = B.solve(M, b, restart=30, inner="fp32", rtol=1e-10, poly_degree=10, poly_roots=roots,
+                         hist_cap=5000)
+    assert d1["status"] == B.OK and d1["rel_resid_true"] <= 1e-10
+    assert d1["iters"] < d0["iters"]
+    true = np.linalg.norm(bb - A.scipy() @ x1.cpu().numpy()) / np.linalg.norm(bb)
+    assert true <= 1e-10
+    ref = L.gmres_ir(A, bb, m=30, rtol=1e-10, inner="fp32", poly_roots=roots, check_mode=1)
+    assert ref.status == L.OK
+    assert abs(d1["iters"] - ref.iters) <= 5
+    k1 = ref.cycle_starts[1] if len(ref.cycle_starts) > 1 else len(ref.hist)
+    assert np.max(np.abs(h1[:k1] - np.array(ref.hist[:k1]))) <= 1e-4
+    assert rel(x1.cpu().numpy(), ref.x) <= 1e-7
