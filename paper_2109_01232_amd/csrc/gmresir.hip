@@ -149,12 +149,13 @@ Layout make_layout(int64_t n, const gmresir_params* p) {
     o = align_up(o + bytes);
     return at;
   };
-  size_t vecT = (size_t)n * L.sT;
+  // every internal vector is padded to ldv rows (vector loads of 2-4 rows)
+  size_t vecT = (size_t)L.ldv * L.sT;
   L.V = take((size_t)L.ldv * (L.m + 1) * L.sS);
   L.wtmp = take(vecT);
   L.w1 = take(vecT);
   L.w2 = take(vecT);
-  L.r64 = take((size_t)n * 8);
+  L.r64 = take((size_t)L.ldv * 8);
   bool need_uz = L.multi || L.poly;
   L.rhat = L.multi ? take(vecT) : 0;
   L.u = L.multi ? take(vecT) : 0;
@@ -494,13 +495,14 @@ struct Ctx {
   void update_proj_dispatch(int k) {
     bool fused = true;
     if (k <= 16) launch_update_proj<16, 16>(k);
-    else if (k <= 32) launch_update_proj<32, 32>(k);
     else if constexpr (sizeof(T) == 8) {
-      if (k <= 56) launch_update_proj<16, 56>(k);
+      if (k <= 32) launch_update_proj<24, 32>(k);
+      else if (k <= 64) launch_update_proj<16, 64>(k);
       else fused = false;
     } else {
-      if (k <= 64) launch_update_proj<64, 64>(k);
-      else if (k <= 128) launch_update_proj<32, 128>(k);
+      if (k <= 32) launch_update_proj<32, 32>(k);
+      else if (k <= 64) launch_update_proj<32, 64>(k);
+      else if (k <= 128) launch_update_proj<16, 128>(k);
       else fused = false;
     }
     if (!fused) {

@@ -122,6 +122,55 @@ struct Quad<bf16_t, float> {
   }
 };
 
+// Two consecutive entries (rows r, r+1; r even) with one 8-byte (fp32),
+// 16-byte (fp64) or 4-byte (bf16) load.
+template <typename S, typename T>
+struct Pair;
+template <>
+struct Pair<float, float> {
+  static __device__ __forceinline__ void load(const float* p, float (&v)[2]) {
+    const float2 q = *(const float2*)p;
+    v[0] = q.x;
+    v[1] = q.y;
+  }
+  static __device__ __forceinline__ void store(float* p, const float (&v)[2]) { *(float2*)p = make_float2(v[0], v[1]); }
+};
+template <>
+struct Pair<double, double> {
+  static __device__ __forceinline__ void load(const double* p, double (&v)[2]) {
+    const double2 q = *(const double2*)p;
+    v[0] = q.x;
+    v[1] = q.y;
+  }
+  static __device__ __forceinline__ void store(double* p, const double (&v)[2]) {
+    *(double2*)p = make_double2(v[0], v[1]);
+  }
+};
+template <>
+struct Pair<bf16_t, float> {
+  static __device__ __forceinline__ void load(const bf16_t* p, float (&v)[2]) {
+    const uint32_t q = *(const uint32_t*)p;
+    v[0] = __uint_as_float(q << 16);
+    v[1] = __uint_as_float(q & 0xffff0000u);
+  }
+};
+
+template <typename T>
+struct QuadStore;
+template <>
+struct QuadStore<float> {
+  static __device__ __forceinline__ void store(float* p, const float (&v)[4]) {
+    *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
+  }
+};
+template <>
+struct QuadStore<double> {
+  static __device__ __forceinline__ void store(double* p, const double (&v)[4]) {
+    *(double2*)p = make_double2(v[0], v[1]);
+    *(double2*)(p + 2) = make_double2(v[2], v[3]);
+  }
+};
+
 // w = A v_j and the partial sums of h1 = V_{j+1}^T w.
 //
 // Per tile: the SpMV products are staged in LDS and summed per row (one
@@ -269,9 +318,12 @@ __global__ __launch_bounds__(BLOCK) void k_dots(int n, const S* __restrict__ V, 
 // second kernel: first-pass update + second-pass projection
 // ---------------------------------------------------------------------------
 
-// Columns c < KREG are held in registers between the update and the
-// projection; columns KREG <= c < k (k <= KACC) are loaded a second time
-// (the rows were just touched, so the reload is served by the caches).
+// Each lane owns two consecutive rows (8-byte loads for fp32).  Columns
+// c < KREG are held in registers between the update and the projection;
+// columns KREG <= c < k (k <= KACC) are loaded a second time (the rows were
+// just touched, so the reload is served by the caches).  Workspace vectors
+// and basis columns are padded to ldv rows, so the pair loads stay in bounds;
+// the padded row is masked out.
 template <typename T, typename S, int KREG, int KACC>
 __global__ __launch_bounds__(BLOCK) void k_update_proj(int n, const T* __restrict__ w_in, T* __restrict__ w_out,
                                                        const S* __restrict__ V, long ldv, int k, State st,
@@ -287,32 +339,52 @@ __global__ __launch_bounds__(BLOCK) void k_update_proj(int n, const T* __restric
   T acc[KACC];
 #pragma unroll
   for (int c = 0; c < KACC; ++c) acc[c] = T(0);
-  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
-    T vr[KREG];
-    T wv = w_in[r];
-    const uint32_t roff = (uint32_t)r * (uint32_t)sizeof(S);
+  for (int r = r0 + 2 * threadIdx.x; r < r1; r += 2 * BLOCK) {
+    const bool two = r + 1 < r1;
+    T wv[2];
+    Pair<T, T>::load(w_in + r, wv);
+    if (!two) wv[1] = T(0);
+    T vr[KREG][2];
 #pragma unroll
     for (int c = 0; c < KREG; ++c)
-      if (c < k) vr[c] = vload<S, T>(V, ldv, c, roff);
+      if (c < k) {
+        Pair<S, T>::load(V + (size_t)c * ldv + r, vr[c]);
+        if (!two) vr[c][1] = T(0);
+      }
 #pragma unroll
     for (int c = 0; c < KREG; ++c)
-      if (c < k) wv -= s_h[c] * vr[c];
+      if (c < k) {
+        wv[0] -= s_h[c] * vr[c][0];
+        wv[1] -= s_h[c] * vr[c][1];
+      }
 #pragma unroll
-    for (int cb = KREG; cb < KACC; cb += 32) {
+    for (int cb = KREG; cb < KACC; cb += 16) {
 #pragma unroll
-      for (int c = cb; c < cb + 32 && c < KACC; ++c)
-        if (c < k) wv -= s_h[c] * vload<S, T>(V, ldv, c, roff);
+      for (int c = cb; c < cb + 16 && c < KACC; ++c)
+        if (c < k) {
+          T v[2];
+          Pair<S, T>::load(V + (size_t)c * ldv + r, v);
+          if (!two) v[1] = T(0);
+          wv[0] -= s_h[c] * v[0];
+          wv[1] -= s_h[c] * v[1];
+        }
       asm volatile("" ::: "memory");
     }
-    w_out[r] = wv;
+    if (two) Pair<T, T>::store(w_out + r, wv);
+    else w_out[r] = wv[0];
 #pragma unroll
     for (int c = 0; c < KREG; ++c)
-      if (c < k) acc[c] += vr[c] * wv;
+      if (c < k) acc[c] += vr[c][0] * wv[0] + vr[c][1] * wv[1];
 #pragma unroll
-    for (int cb = KREG; cb < KACC; cb += 32) {
+    for (int cb = KREG; cb < KACC; cb += 16) {
 #pragma unroll
-      for (int c = cb; c < cb + 32 && c < KACC; ++c)
-        if (c < k) acc[c] += vload<S, T>(V, ldv, c, roff) * wv;
+      for (int c = cb; c < cb + 16 && c < KACC; ++c)
+        if (c < k) {
+          T v[2];
+          Pair<S, T>::load(V + (size_t)c * ldv + r, v);
+          if (!two) v[1] = T(0);
+          acc[c] += v[0] * wv[0] + v[1] * wv[1];
+        }
       asm volatile("" ::: "memory");
     }
   }
@@ -426,6 +498,8 @@ __device__ __forceinline__ void givens_tail(const State& st, int j, int kmax, T 
   }
 }
 
+// Each lane owns four consecutive rows (16-byte loads for fp32); the padded
+// rows past n are masked out.
 template <typename T, typename S>
 __global__ __launch_bounds__(BLOCK) void k_update_norm(int n, const T* __restrict__ w_in, T* __restrict__ wtmp,
                                                        const S* __restrict__ V, long ldv, int j, State st,
@@ -440,13 +514,28 @@ __global__ __launch_bounds__(BLOCK) void k_update_norm(int n, const T* __restric
   int r0, r1;
   block_rows(n, r0, r1);
   T nrm = T(0);
-  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
-    T wv = w_in[r];
-    const uint32_t roff = (uint32_t)r * (uint32_t)sizeof(S);
-#pragma unroll 8
-    for (int c = 0; c < k; ++c) wv -= s_h[c] * vload<S, T>(V, ldv, c, roff);
-    wtmp[r] = wv;
-    nrm += wv * wv;
+  for (int r = r0 + 4 * threadIdx.x; r < r1; r += 4 * BLOCK) {
+    const int nv = r1 - r < 4 ? r1 - r : 4;
+    T wv[4];
+    Quad<T, T>::load(w_in + r, wv);
+#pragma unroll 4
+    for (int c = 0; c < k; ++c) {
+      T v[4];
+      Quad<S, T>::load(V + (size_t)c * ldv + r, v);
+      const T h = s_h[c];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) wv[i] -= h * v[i];
+    }
+    if (nv == 4) {
+      QuadStore<T>::store(wtmp + r, wv);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) nrm += wv[i] * wv[i];
+    } else {
+      for (int i = 0; i < nv; ++i) {
+        wtmp[r + i] = wv[i];
+        nrm += wv[i] * wv[i];
+      }
+    }
   }
   const T bs = block_sum(nrm, s_scr);
   if (threadIdx.x == 0) s_vals[0] = bs;
@@ -660,7 +749,8 @@ __global__ __launch_bounds__(BLOCK) void k_inner_resid(Csr A, const T* __restric
   store_partials(s_vals, 1, part);
 }
 
-// x += gamma * (V_k y) with V_k y accumulated in inner precision (Algorithm 2, line 4).
+// x += gamma * (V_k y) with V_k y accumulated in inner precision (Algorithm 2,
+// line 4).  Four rows per lane; x (the caller's vector) is accessed per element.
 template <typename T, typename S>
 __global__ __launch_bounds__(BLOCK) void k_correct_x(int n, const S* __restrict__ V, long ldv, State st,
                                                      double* __restrict__ x) {
@@ -672,16 +762,22 @@ __global__ __launch_bounds__(BLOCK) void k_correct_x(int n, const S* __restrict_
   __syncthreads();
   int r0, r1;
   block_rows(n, r0, r1);
-  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
-    T u = T(0);
-    const uint32_t roff = (uint32_t)r * (uint32_t)sizeof(S);
-#pragma unroll 8
-    for (int c = 0; c < k; ++c) u += vload<S, T>(V, ldv, c, roff) * s_y[c];
-    x[r] = x[r] + gamma * (double)u;
+  for (int r = r0 + 4 * threadIdx.x; r < r1; r += 4 * BLOCK) {
+    const int nv = r1 - r < 4 ? r1 - r : 4;
+    T u[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 4
+    for (int c = 0; c < k; ++c) {
+      T v[4];
+      Quad<S, T>::load(V + (size_t)c * ldv + r, v);
+      const T yc = s_y[c];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) u[i] += v[i] * yc;
+    }
+    for (int i = 0; i < nv; ++i) x[r + i] = x[r + i] + gamma * (double)u[i];
   }
 }
 
-// z = V_k y in inner precision.
+// z = V_k y in inner precision (z is a workspace vector padded to ldv).
 template <typename T, typename S>
 __global__ __launch_bounds__(BLOCK) void k_vy(int n, const S* __restrict__ V, long ldv, State st, T* __restrict__ z) {
   __shared__ T s_y[MAX_RESTART];
@@ -690,12 +786,18 @@ __global__ __launch_bounds__(BLOCK) void k_vy(int n, const S* __restrict__ V, lo
   __syncthreads();
   int r0, r1;
   block_rows(n, r0, r1);
-  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
-    T u = T(0);
-    const uint32_t roff = (uint32_t)r * (uint32_t)sizeof(S);
-#pragma unroll 8
-    for (int c = 0; c < k; ++c) u += vload<S, T>(V, ldv, c, roff) * s_y[c];
-    z[r] = u;
+  for (int r = r0 + 4 * threadIdx.x; r < r1; r += 4 * BLOCK) {
+    const int nv = r1 - r < 4 ? r1 - r : 4;
+    T u[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 4
+    for (int c = 0; c < k; ++c) {
+      T v[4];
+      Quad<S, T>::load(V + (size_t)c * ldv + r, v);
+      const T yc = s_y[c];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) u[i] += v[i] * yc;
+    }
+    for (int i = 0; i < nv; ++i) z[r + i] = u[i];
   }
 }
 
