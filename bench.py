@@ -81,6 +81,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--suite", action="store_true",
+                    help="also time the other workloads (150^3 anisotropic + polynomial, 128^3 27-point "
+                         "bf16/fp32/fp64, 64^2 parity system); one JSON line each, after the main line")
+    ap.add_argument("--suite-only", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -100,6 +104,10 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     B.lib()
+
+    if args.suite_only:
+        suite(args)
+        return
 
     if args.copy_calibration:
         # plain copy of a known size (256 MiB read + 256 MiB written) for the counter scaling
@@ -213,6 +221,76 @@ def main():
         out["cpu_baseline"] = cpu_baseline(system, d_ir["iters"])
 
     print(json.dumps(out), flush=True)
+    if args.suite:
+        suite(args)
+
+
+def time_solves(M, b, p, roots, ws, steps):
+    import torch
+
+    from paper_2109_01232_amd import binding as B
+
+    x = torch.zeros_like(b)
+    x.zero_()
+    B.gmresir_solve(M, b, x, p, poly_roots=roots, ws=ws)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.zero_()
+        st, d, _ = B.gmresir_solve(M, b, x, p, poly_roots=roots, ws=ws)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, st, d, x
+
+
+def suite(args):
+    """Time-to-1e-10 on the other configurations (separate JSON lines)."""
+    import numpy as np
+    import torch
+
+    from paper_2109_01232_amd import binding as B
+    from paper_2109_01232_amd import problems as P
+
+    steps = max(1, min(args.steps, 3))
+    ws = B.Workspace()
+    cases = []
+    s3 = P.aniso3d_system(0)
+    cases.append(("aniso3d_150_7pt", s3, [("fp64", "fp64", 100, 0), ("fp32", "fp32", 100, 0),
+                                          ("fp32", "fp32", 100, 10), ("fp32", "fp32", 100, 20),
+                                          ("fp32", "fp32", 100, 30), ("fp32", "fp32", 100, 40)]))
+    s4 = P.varcoef27_system(0)
+    cases.append(("varcoef27_128", s4, [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0), ("fp32", "bf16", 50, 0)]))
+    s1 = P.parity_system()
+    cases.append(("convdiff2d_64_parity", s1, [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0),
+                                               ("fp32", "bf16", 50, 0)]))
+    for name, sysm, cfgs in cases:
+        log("suite", name)
+        M = B.Matrix.from_csr(sysm.A)
+        b = torch.from_numpy(sysm.b).cuda()
+        for inner, basis, m, deg in cfgs:
+            roots, t_setup = None, 0.0
+            if deg > 0:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                roots = B.gmresir_poly_setup(M, deg, seed=12345, ws=ws)
+                torch.cuda.synchronize()
+                t_setup = time.perf_counter() - t0
+            p = B.make_params(restart=m, inner=inner, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg)
+            t, st, d, x = time_solves(M, b, p, roots, ws, steps)
+            xs = x.cpu().numpy()
+            true = float(np.linalg.norm(sysm.b - sysm.A.scipy() @ xs) / np.linalg.norm(sysm.b))
+            prof = B.make_params(restart=m, inner=inner, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg,
+                                 profile=1)
+            x.zero_()
+            _, dp, _ = B.gmresir_solve(M, b, x, prof, poly_roots=roots, ws=ws)
+            gbps = {c: (dp["cat_bytes"][c] / dp["cat_time_s"][c] / 1e9) for c in B.CATEGORIES
+                    if dp["cat_time_s"][c] > 0}
+            rec = {"suite": name, "N": sysm.A.n, "nnz": sysm.A.nnz, "inner": inner, "basis": basis, "restart": m,
+                   "poly_degree": deg, "status": st, "time_to_1e-10_s": t, "poly_setup_s": t_setup,
+                   "iters": d["iters"], "refinements": d["refinements"], "rel_resid_true": true,
+                   "sol_err_vs_u": float(np.linalg.norm(xs - sysm.u) / np.linalg.norm(sysm.u)),
+                   "GBps_by_category": gbps}
+            print(json.dumps(rec), flush=True)
+        del M
 
 
 if __name__ == "__main__":
