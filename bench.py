@@ -168,6 +168,8 @@ def main():
         },
         "iters": d_ir["iters"],
         "refinements": d_ir["refinements"],
+        "status": B.status_string(d_ir["status"]),
+        "converged": bool(true_resid <= 1e-10),
         "rel_resid_true": true_resid,
         "sol_err_vs_u": sol_err,
     }

@@ -60,11 +60,12 @@ enum gmresir_precision { GMRESIR_FP64 = 0, GMRESIR_FP32 = 1, GMRESIR_BF16 = 2 };
 enum gmresir_category {
   GMRESIR_CAT_SPMV_PROJ = 0,   /* w = A v_j and h1 = V^T w (first CGS pass projection) */
   GMRESIR_CAT_UPDATE_PROJ = 1, /* w -= V h1 and h2 = V^T w (second pass projection) */
-  GMRESIR_CAT_UPDATE_NORM = 2, /* w -= V h2, ||w||, Hessenberg column and Givens update */
+  GMRESIR_CAT_UPDATE_NORM = 2, /* w -= V h2 and the partial sums of ||w||^2 */
   GMRESIR_CAT_POLY = 3,        /* SpMV steps of p(A) */
   GMRESIR_CAT_REFINE = 4,      /* correction x += gamma V y, r = b - A x (fp64), cast of r */
   GMRESIR_CAT_OTHER = 5,       /* fallbacks for restart lengths beyond the fused limit */
-  GMRESIR_NCAT = 6
+  GMRESIR_CAT_TAIL = 6,        /* one-block tails: sums of h1, h2, ||w||^2; Hessenberg column, Givens update */
+  GMRESIR_NCAT = 7
 };
 
 typedef struct gmresir_matrix gmresir_matrix; /* opaque host-side handle */

@@ -22,8 +22,8 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "gmresir.h")
 OK, NOT_CONVERGED, STAGNATED, BREAKDOWN = 0, 1, 2, 3
 ERR_INVALID_ARG, ERR_HIP, ERR_WORKSPACE, ERR_NUMERIC, ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 FP64, FP32, BF16 = 0, 1, 2
-NCAT = 6
-CATEGORIES = ("spmv_proj", "update_proj", "update_norm", "poly", "refine", "other")
+NCAT = 7
+CATEGORIES = ("spmv_proj", "update_proj", "update_norm", "poly", "refine", "other", "tail")
 PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
 

@@ -1,6 +1,6 @@
 // Device-side building blocks of libgmresir for gfx950 (wave64, 256 CUs in
 // 8 XCDs): basis storage types, wave/block reductions, the deterministic
-// grid-wide "last block" reduction, and the shared device state of a cycle.
+// two-kernel grid reduction, and the shared device state of a cycle.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -93,12 +93,13 @@ struct StateHdr {
   int32_t cycle_k;      // k and flags of the last finished cycle (kept across
   int32_t cycle_flags;  // the reset a new cycle start does)
   int32_t pad[3];
-  uint32_t counter[8];  // tickets of the grid-wide reductions (reset by the last block)
+  uint32_t spare[8];
 };
 
 struct State {
   StateHdr* hdr;
-  double* h1;    // m+1   first-pass projection coefficients
+  double* h1;    // m+1   first-pass projection coefficients (even iterations j)
+  double* h1x;   // m+1   the same for odd j (the Givens step of j-1 reads its h1 while h1 of j is written)
   double* h2;    // m+1   second-pass projection coefficients
   double* Hbar;  // (m+1) x m unrotated Hessenberg matrix, column-major, ld
   double* R;     // (m+1) x m rotated (triangular) columns
@@ -108,6 +109,7 @@ struct State {
   double* y;     // m     least-squares solution of the finished cycle
   double* hist;  // m     |g_{j+1}| / gamma_in per step
   int ld;        // m+1
+  __host__ __device__ double* h1_of(int j) const { return (j & 1) ? h1x : h1; }
 };
 
 // CSR operand of the SpMV kernels; vals has element type MT.
@@ -119,6 +121,14 @@ struct Csr {
   const void* vals;
   const int* tile_row;  // ntiles+1 row boundaries
 };
+
+// Dynamic LDS of a kernel (sized at launch: the SpMV product buffer holds the
+// largest tile of the matrix, the back substitution its triangle).
+template <typename T>
+__device__ __forceinline__ T* dyn_lds() {
+  extern __shared__ __align__(16) unsigned char gir_dyn_lds[];
+  return (T*)gir_dyn_lds;
+}
 
 // ---------------------------------------------------------------------------
 // reductions
@@ -172,6 +182,21 @@ __device__ __forceinline__ void block_reduce_vec(const T (&acc)[NV], int nv, T* 
   __syncthreads();
 }
 
+// Same as block_sum for any block size up to 1024 threads.
+template <typename T>
+__device__ __forceinline__ T block_sum_any(T v, T* lds /* 16 */) {
+  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+  const int nw = blockDim.x / WAVE;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  T s = lds[0];
+  for (int w = 1; w < nw; ++w) s += lds[w];
+  __syncthreads();
+  return s;
+}
+
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* lds /* NWAVES */) {
   const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
@@ -195,20 +220,55 @@ __device__ __forceinline__ T block_sum(T v, T* lds /* NWAVES */) {
 constexpr int MAX_BLOCKS = 1024;
 constexpr int RED_BATCH = 4;                   // columns reduced per wave and batch
 constexpr int RED_LOADS = MAX_BLOCKS / WAVE;   // partials per lane and column
+constexpr int PART_COLS = 136;                 // partial columns in the workspace (>= 129 + 1)
+constexpr int NORM_SLOT = PART_COLS - 1;       // column of the ||w''||^2 partials of k_update_norm
 
 template <typename T>
 __device__ __forceinline__ void store_partials(const T* vals, int nv, T* part) {
   for (int c = threadIdx.x; c < nv; c += BLOCK) part[(size_t)c * MAX_BLOCKS + blockIdx.x] = vals[c];
 }
 
+// Sum of one column of partials by one wave: lane l adds b = l + 64 i in
+// order of i, then the lanes by a fixed butterfly (the order reduce_partials
+// uses, so both give the same bits).  Every lane returns the sum.
+template <typename T>
+__device__ __forceinline__ T wave_reduce_column(const T* col, int B) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  T s = T(0);
+#pragma unroll
+  for (int i = 0; i < RED_LOADS; ++i) {
+    const int b = lane + WAVE * i;
+    const int bc = b < B ? b : B - 1;
+    const T v = col[bc];
+    s += (b < B) ? v : T(0);
+  }
+  return wave_sum(s);
+}
+
 // out[c] = sum over the B producer blocks of part[c][b], one wave per column:
 // lane l sums b = l + 64 i in order of i, then the lanes by a fixed butterfly.
-// All loads of a batch are issued before any add.  out is LDS; ends with a
-// barrier.
+// All loads of a batch are issued before any add.  With extra != nullptr the
+// last wave first sums one more column, out[nv] = sum of extra[b], b < nE, in
+// the same order (bitwise the result of a separate call with nv = 1).  out is
+// LDS; ends with a barrier.
 template <typename T>
-__device__ __forceinline__ void reduce_partials(const T* part, int nv, int B, T* out) {
-  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+__device__ __forceinline__ void reduce_partials(const T* part, int nv, int B, T* out, const T* extra = nullptr,
+                                                int nE = 0) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int nwaves = blockDim.x / WAVE;
+  if (extra && wid == nwaves - 1) {
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < RED_LOADS; ++i) {
+      const int b = lane + WAVE * i;
+      const int bc = b < nE ? b : nE - 1;
+      const T v = extra[bc];
+      s += (b < nE) ? v : T(0);
+    }
+    const T t = wave_sum(s);
+    if (lane == 0) out[nv] = t;
+  }
   for (int c0 = wid * RED_BATCH; c0 < nv; c0 += nwaves * RED_BATCH) {
     T s[RED_BATCH];
 #pragma unroll

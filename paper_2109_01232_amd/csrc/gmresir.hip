@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <vector>
 
@@ -30,13 +31,13 @@ struct gmresir_matrix {
   float* vals32;
   int32_t* tile_row;
   int ntiles;
+  int lds_nnz;  // largest nonzero count of a tile that is staged in LDS (<= TILE_NNZ)
   int device;
 };
 
 namespace {
 
 constexpr int MAX_GRID = 1024;  // <= MAX_BLOCKS (partials per reduction)
-constexpr int PSTRIDE = 136;  // >= 129 partial values per block
 constexpr size_t ALIGN = 256;
 
 #define HIP_TRY(expr)                                                              \
@@ -69,19 +70,19 @@ int device_cus(int dev) {
 
 int resident_grid(const void* kern, size_t smem) {
   static std::mutex mu;
-  static std::map<std::pair<int, const void*>, int> cache;
+  static std::map<std::tuple<int, const void*, size_t>, int> cache;
   int dev = 0;
   (void)hipGetDevice(&dev);
   {
     std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find({dev, kern});
+    auto it = cache.find({dev, kern, smem});
     if (it != cache.end()) return it->second;
   }
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, BLOCK, smem) != hipSuccess || nb <= 0) nb = 1;
   int g = std::min(MAX_GRID, device_cus(dev) * nb);
   std::lock_guard<std::mutex> lk(mu);
-  cache[{dev, kern}] = g;
+  cache[{dev, kern, smem}] = g;
   return g;
 }
 
@@ -91,7 +92,9 @@ int grid_rows(const void* kern, int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, want));
 }
 
-int grid_tiles(const void* kern, int ntiles) { return std::max(1, std::min(resident_grid(kern, 0), ntiles)); }
+int grid_tiles(const void* kern, int ntiles, size_t smem) {
+  return std::max(1, std::min(resident_grid(kern, smem), ntiles));
+}
 
 Csr csr_of(const gmresir_matrix* A, bool fp64) {
   Csr c;
@@ -164,10 +167,10 @@ Layout make_layout(int64_t n, const gmresir_params* p) {
   L.p0 = L.poly ? take(vecT) : 0;
   L.p1 = L.poly ? take(vecT) : 0;
   L.p2 = L.poly ? take(vecT) : 0;
-  L.part = take((size_t)MAX_BLOCKS * PSTRIDE * 8);
+  L.part = take((size_t)MAX_BLOCKS * PART_COLS * 8);
   L.hdr = take(sizeof(StateHdr));
   size_t m = L.m;
-  size_t arr = (2 * (m + 2) + 2 * (m + 1) * m + 2 * m + (m + 2) + 2 * m) * sizeof(double);
+  size_t arr = (3 * (m + 2) + 2 * (m + 1) * m + 2 * m + (m + 2) + 2 * m) * sizeof(double);
   L.arr = take(arr);
   L.total = o;
   return L;
@@ -180,6 +183,8 @@ State state_of(char* ws, const Layout& L) {
   size_t m = L.m;
   st.ld = (int)(m + 1);
   st.h1 = a;
+  a += m + 2;
+  st.h1x = a;
   a += m + 2;
   st.h2 = a;
   a += m + 2;
@@ -383,6 +388,8 @@ struct Ctx {
     A64 = csr_of(A, true);
   }
 
+  size_t lds_in() const { return (size_t)A->lds_nnz * sizeof(T); }   // SpMV products, inner precision
+  size_t lds_64() const { return (size_t)A->lds_nnz * sizeof(double); }
   double sT() const { return (double)sizeof(T); }
   double sS() const { return (double)sizeof(S); }
   double spmv_bytes() const { return (sT() + 4.0) * A->nnz + 4.0 * (A->n + 1); }
@@ -399,7 +406,7 @@ struct Ctx {
 
   // y_out = p(A) src; scaled: src holds the unnormalised next basis vector
   // (wtmp, scaled by inv_h and rounded to the basis type, written into V[:, j]).
-  void run_poly(T* src, bool scaled, int j, T* y_out, int check_done, int cat) {
+  void run_poly(T* src, bool scaled, int j, T* y_out, int check_done, int cat, int nB = 0) {
     for (size_t s = 0; s < prog.size(); ++s) {
       const PStep& ps = prog[s];
       PolyCoef<T> cf;
@@ -424,53 +431,67 @@ struct Ctx {
                  (write_v ? sS() * n : 0.0);
       if (scaled && ps.x == PB_SRC) {
         auto kern = k_poly_step<T, S, true>;
-        int g = grid_tiles((const void*)kern, Ain.ntiles);
+        int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
         prof->run(cat, b, [&] {
-          hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, Ain, X, V, L.ldv, j, write_v, W, w_scaled, y_out, D,
-                             cf, st, check_done);
+          hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, write_v, W, w_scaled, y_out, D,
+                             cf, st, check_done, (const T*)norm_part(), nB);
         });
       } else {
         auto kern = k_poly_step<T, S, false>;
-        int g = grid_tiles((const void*)kern, Ain.ntiles);
+        int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
         prof->run(cat, b, [&] {
-          hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, Ain, X, V, L.ldv, j, 0, W, w_scaled, y_out, D, cf,
-                             st, check_done);
+          hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, 0, W, w_scaled, y_out, D, cf,
+                             st, check_done, (const T*)norm_part(), nB);
         });
       }
     }
   }
 
+  // partials of ||w''||^2 written by k_update_norm (their own column, so
+  // they survive the projections of the next iteration)
+  T* norm_part() const { return part + (size_t)NORM_SLOT * MAX_BLOCKS; }
+  int norm_grid() const { return grid_rows((const void*)k_update_norm<T, S>, n); }
+
+  // nB: producer blocks of the previous iteration's norm partials (0 at a
+  // cycle start); the tail also makes the Givens step of iteration j - 1.
   template <int SLOTS, bool SCALED>
-  void launch_spmv_proj(const T* src, int j) {
+  void launch_spmv_proj(const T* src, int j, int kmax, int nB) {
     constexpr int KMAX = NWAVES * SLOTS;
     auto kern = k_spmv_proj<T, S, SLOTS, SCALED>;
-    int g = grid_tiles((const void*)kern, Ain.ntiles);
+    int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
     const int C = std::min(j + 1, KMAX);
     // basis columns read from memory: all handled columns but the new one (SCALED)
     const int nread = SCALED ? std::min(j, C) : C;
     double b = spmv_bytes() + sT() * n * 2 + sS() * n * nread + (SCALED ? sS() * n : 0.0);
     prof->run(GMRESIR_CAT_SPMV_PROJ, b, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, Ain, src, V, L.ldv, j, w1, st, part);
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, src, V, L.ldv, j, w1, st, part,
+                         (const T*)norm_part(), nB);
     });
-    reduce_h(GMRESIR_CAT_SPMV_PROJ, g, C, st.h1, -1);
+    auto tail = k_reduce_h1_givens<T>;
+    const int tg = (C + NWAVES - 1) / NWAVES + (j > 0 ? 1 : 0);
+    prof->run(GMRESIR_CAT_TAIL, 0.0, [&] {
+      hipLaunchKernelGGL(tail, dim3(tg), dim3(BLOCK), 0, stream, (const T*)part, C, g, (const T*)norm_part(), nB, st,
+                         j - 1, kmax);
+    });
   }
 
-  void reduce_h(int cat, int producer_grid, int nv, double* h, int last_to) {
-    auto kern = k_reduce_h<T>;
-    prof->run(cat, 0.0, [&] {
-      hipLaunchKernelGGL(kern, dim3(1), dim3(512), 0, stream, (const T*)part, nv, producer_grid, h, last_to, st, 1);
+  void reduce_h(int cat, int producer_grid, int nv, double* h) {
+    auto kern = k_reduce_cols<T>;
+    const int tg = (nv + NWAVES - 1) / NWAVES;
+    prof->run(cat == GMRESIR_CAT_OTHER ? cat : GMRESIR_CAT_TAIL, 0.0, [&] {
+      hipLaunchKernelGGL(kern, dim3(tg), dim3(BLOCK), 0, stream, (const T*)part, nv, producer_grid, h, st, 1);
     });
   }
 
   template <bool SCALED>
-  void spmv_proj_dispatch(const T* src, int j) {
+  void spmv_proj_dispatch(const T* src, int j, int kmax, int nB) {
     const int k = j + 1;
-    if (k <= 16) launch_spmv_proj<4, SCALED>(src, j);
-    else if (k <= 32) launch_spmv_proj<8, SCALED>(src, j);
-    else if (k <= 64) launch_spmv_proj<16, SCALED>(src, j);
-    else launch_spmv_proj<32, SCALED>(src, j);
+    if (k <= 16) launch_spmv_proj<4, SCALED>(src, j, kmax, nB);
+    else if (k <= 32) launch_spmv_proj<8, SCALED>(src, j, kmax, nB);
+    else if (k <= 64) launch_spmv_proj<16, SCALED>(src, j, kmax, nB);
+    else launch_spmv_proj<32, SCALED>(src, j, kmax, nB);
     // columns beyond the fused limit (V[:, j] is in memory by now)
-    for (int c0 = 128; c0 < k; c0 += 64) dots(c0, std::min(64, k - c0), w1, st.h1, GMRESIR_CAT_OTHER);
+    for (int c0 = 128; c0 < k; c0 += 64) dots(c0, std::min(64, k - c0), w1, st.h1_of(j), GMRESIR_CAT_OTHER);
   }
 
   void dots(int c0, int nc, const T* w, double* h, int cat) {
@@ -479,64 +500,74 @@ struct Ctx {
     prof->run(cat, sS() * n * nc + sT() * n, [&] {
       hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, V, L.ldv, c0, nc, w, st, 1, part);
     });
-    reduce_h(cat, g, nc, h + c0, -1);
+    reduce_h(cat, g, nc, h + c0);
   }
 
-  template <int KREG, int KACC>
+  template <int SLOTS, int R>
   void launch_update_proj(int k) {
-    auto kern = k_update_proj<T, S, KREG, KACC>;
+    auto kern = k_update_proj<T, S, SLOTS, R>;
     int g = grid_rows((const void*)kern, n);
     prof->run(GMRESIR_CAT_UPDATE_PROJ, sT() * n * 2 + sS() * n * k, [&] {
       hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w1, w2, V, L.ldv, k, st, part);
     });
-    reduce_h(GMRESIR_CAT_UPDATE_PROJ, g, k, st.h2, -1);
+    reduce_h(GMRESIR_CAT_UPDATE_PROJ, g, k, st.h2);
   }
 
   void update_proj_dispatch(int k) {
-    bool fused = true;
-    if (k <= 16) launch_update_proj<16, 16>(k);
-    else if constexpr (sizeof(T) == 8) {
-      if (k <= 32) launch_update_proj<24, 32>(k);
-      else if (k <= 64) launch_update_proj<16, 64>(k);
-      else fused = false;
-    } else {
-      if (k <= 32) launch_update_proj<32, 32>(k);
-      else if (k <= 64) launch_update_proj<32, 64>(k);
-      else if (k <= 128) launch_update_proj<16, 128>(k);
-      else fused = false;
-    }
-    if (!fused) {
+    // fp64 values take two registers: half the rows per lane
+    constexpr int R4 = sizeof(T) == 8 ? 2 : 4;
+    constexpr int R2 = sizeof(T) == 8 ? 1 : 2;
+    if (k <= 16) launch_update_proj<4, R4>(k);
+    else if (k <= 32) launch_update_proj<8, R4>(k);
+    else if (k <= 48) launch_update_proj<12, R4>(k);
+    else if (k <= 64) launch_update_proj<16, R4>(k);
+    else if (k <= 96) launch_update_proj<24, R2>(k);
+    else if (k <= 128) launch_update_proj<32, R2>(k);
+    else {
       auto kern = k_update<T, S>;
       int g = grid_rows((const void*)kern, n);
       prof->run(GMRESIR_CAT_OTHER, sT() * n * 2 + sS() * n * k, [&] {
-        hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w1, w2, V, L.ldv, k, (const double*)st.h1, st);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w1, w2, V, L.ldv, k, (const double*)st.h1_of(k - 1),
+                           st);
       });
       for (int c0 = 0; c0 < k; c0 += 64) dots(c0, std::min(64, k - c0), w2, st.h2, GMRESIR_CAT_OTHER);
     }
   }
 
-  void update_norm(int j, int kmax) {
+  void update_norm(int j) {
     auto kern = k_update_norm<T, S>;
     int g = grid_rows((const void*)kern, n);
     prof->run(GMRESIR_CAT_UPDATE_NORM, sT() * n * 2 + sS() * n * (j + 1), [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w2, wtmp, V, L.ldv, j, st, part);
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w2, wtmp, V, L.ldv, j, st, norm_part());
     });
+  }
+
+  // Givens step of the last iteration of a cycle (the others run in the
+  // tail after the next iteration's SpMV)
+  void norm_givens(int j, int kmax) {
     auto tail = k_norm_givens<T>;
-    prof->run(GMRESIR_CAT_UPDATE_NORM, 0.0, [&] {
-      hipLaunchKernelGGL(tail, dim3(1), dim3(BLOCK), 0, stream, (const T*)part, g, st, j, kmax);
+    prof->run(GMRESIR_CAT_TAIL, 0.0, [&] {
+      hipLaunchKernelGGL(tail, dim3(1), dim3(BLOCK), 0, stream, (const T*)norm_part(), norm_grid(), st, j, kmax);
     });
   }
 
   // one inner iteration j of a cycle of at most kmax steps
   void iteration(int j, int kmax) {
+    const int nB = j > 0 ? norm_grid() : 0;
     if (poly_on) {
-      run_poly(wtmp, true, j, z, 1, GMRESIR_CAT_POLY);
-      spmv_proj_dispatch<false>(z, j);
+      run_poly(wtmp, true, j, z, 1, GMRESIR_CAT_POLY, nB);
+      spmv_proj_dispatch<false>(z, j, kmax, nB);
     } else {
-      spmv_proj_dispatch<true>(wtmp, j);
+      spmv_proj_dispatch<true>(wtmp, j, kmax, nB);
     }
     update_proj_dispatch(j + 1);
-    update_norm(j, kmax);
+    update_norm(j);
+  }
+
+  // the Arnoldi steps of one cycle, ending with its last Givens step
+  void cycle(int kmax) {
+    for (int j = 0; j < kmax; ++j) iteration(j, kmax);
+    norm_givens(kmax - 1, kmax);
   }
 
   void backsolve(int kmax) {
@@ -578,9 +609,9 @@ struct Ctx {
 
   void resid64(const double* x, const double* b) {
     auto kern = k_resid64;
-    int g = grid_tiles((const void*)kern, A64.ntiles);
+    int g = grid_tiles((const void*)kern, A64.ntiles, lds_64());
     prof->run(GMRESIR_CAT_REFINE, 12.0 * A->nnz + 4.0 * (A->n + 1) + 8.0 * n * 3, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, A64, x, b, r64, (double*)part);
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), lds_64(), stream, A64, x, b, r64, (double*)part);
     });
     sqrt_tail(g, &st.hdr->gamma);
   }
@@ -628,9 +659,9 @@ struct Ctx {
 
   void inner_resid() {
     auto kern = k_inner_resid<T>;
-    int g = grid_tiles((const void*)kern, Ain.ntiles);
+    int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
     prof->run(GMRESIR_CAT_REFINE, spmv_bytes() + sT() * n * 3, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, Ain, (const T*)u, (const T*)rhat, wtmp, part);
+      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, (const T*)u, (const T*)rhat, wtmp, part);
     });
     cycle_tail(g);
   }
@@ -712,7 +743,7 @@ int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresi
     int first = 1;
     while (used < budget) {
       const int kmax = (int)std::min<int64_t>(m, budget - used);
-      for (int j = 0; j < kmax; ++j) c.iteration(j, kmax);
+      c.cycle(kmax);
       c.backsolve(kmax);
       if (single && !L.poly) {
         c.correct_x(x, kmax);
@@ -807,7 +838,7 @@ int arnoldi32(const gmresir_matrix* A, const double* src, int steps, char* ws, c
   Ctx<float, float> c(A, ws, L, stream, &prof);
   c.init(0.0, 0, 1.0);
   c.cast(src);
-  for (int j = 0; j < steps; ++j) c.iteration(j, steps);
+  c.cycle(steps);
   if (int e = c.read_hdr(H)) return e;
   if (hbar) {
     hbar->assign((size_t)(steps + 1) * c.st.ld, 0.0);
@@ -847,7 +878,7 @@ bool ws_ok(const void* ws, size_t have, size_t need) {
 
 extern "C" {
 
-int32_t gmresir_abi_version(void) { return 1; }
+int32_t gmresir_abi_version(void) { return 2; }
 
 const char* gmresir_last_error(void) { return gir::last_error(); }
 
@@ -912,6 +943,11 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
     r0 = r;
   }
   const int ntiles = (int)tiles.size() - 1;
+  int lds_nnz = 1;
+  for (int t = 0; t < ntiles; ++t) {
+    const int len = rp[tiles[t + 1]] - rp[tiles[t]];
+    if (len <= TILE_NNZ) lds_nnz = std::max(lds_nnz, len);
+  }
   if (ntiles > max_tiles(n, nnz)) {
     set_error("internal: tile bound exceeded");
     return GMRESIR_ERR_INVALID_ARG;
@@ -935,6 +971,7 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
   A->vals32 = v32;
   A->tile_row = tr;
   A->ntiles = ntiles;
+  A->lds_nnz = lds_nnz;
   A->device = 0;
   (void)hipGetDevice(&A->device);
   *out = A;
@@ -962,12 +999,14 @@ int gmresir_spmv(const gmresir_matrix* A, int32_t prec, const void* x, void* y, 
   hipStream_t s = (hipStream_t)stream;
   if (prec == GMRESIR_FP64) {
     auto kern = k_spmv<double>;
-    int g = grid_tiles((const void*)kern, A->ntiles);
-    hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, s, csr_of(A, true), (const double*)x, (double*)y);
+    const size_t smem = (size_t)A->lds_nnz * sizeof(double);
+    int g = grid_tiles((const void*)kern, A->ntiles, smem);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), smem, s, csr_of(A, true), (const double*)x, (double*)y);
   } else if (prec == GMRESIR_FP32) {
     auto kern = k_spmv<float>;
-    int g = grid_tiles((const void*)kern, A->ntiles);
-    hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, s, csr_of(A, false), (const float*)x, (float*)y);
+    const size_t smem = (size_t)A->lds_nnz * sizeof(float);
+    int g = grid_tiles((const void*)kern, A->ntiles, smem);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), smem, s, csr_of(A, false), (const float*)x, (float*)y);
   } else {
     set_error("gmresir_spmv: prec must be FP64 or FP32");
     return GMRESIR_ERR_INVALID_ARG;

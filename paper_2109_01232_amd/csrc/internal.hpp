@@ -17,9 +17,12 @@ int harmonic_ritz_leja(int k, const double* Hbar_colmajor, int ld, double* roots
 void set_error(const char* fmt, ...);
 const char* last_error();
 
-// Row tiles of the SpMV kernels: at most this many rows / nonzeros per tile.
+// Row tiles of the SpMV kernels: at most this many rows / nonzeros per tile
+// (2560 nonzeros: 512 rows of a 5-point stencil, ~95 rows of a 27-point one;
+// the LDS product buffer then allows 8 blocks per CU).
 constexpr int TILE_ROWS = 512;
-constexpr int TILE_NNZ = 6144;
+constexpr int TILE_NNZ = 2560;
+constexpr int SPMV_UNROLL = 5;  // nonzeros per thread whose loads are issued together
 
 // Upper bound of the number of tiles (every tile holds at least one row).
 inline int64_t max_tiles(int64_t n, int64_t nnz) {

@@ -2,18 +2,22 @@
 //
 // One inner GMRES iteration (Algorithm 1 with two classical Gram-Schmidt
 // passes, Section "GMRES") is three kernels that each sweep the Krylov basis
-// V once -- the minimum for two-pass CGS:
+// V once -- the minimum for two-pass CGS -- plus two one-block tails that
+// finish the cross-block sums:
 //   k_spmv_proj    w = A v_j (row-tiled CSR SpMV, products staged in LDS)
 //                  and h1 = V^T w from the same rows (first-pass projection).
-//                  v_j itself is formed on the fly as round(wtmp * inv_h)
+//                  v_j itself is formed on the fly as round(wtmp / ||wtmp||)
 //                  and stored into V, so no separate normalisation pass.
+//   k_reduce_h1_givens  sums h1 (one wave per column) and, in one more
+//                  block, forms the previous Hessenberg column, applies the
+//                  earlier Givens rotations, makes the new one and updates
+//                  the implicit residual (the paper's host-side least-squares
+//                  step, moved to the device so a cycle needs no host round
+//                  trip).
 //   k_update_proj  w' = w - V h1 and h2 = V^T w' (each row of V is loaded
 //                  into registers once and used for both).
-//   k_update_norm  w'' = w' - V h2 and ||w''||; the last block then forms the
-//                  Hessenberg column h1 + h2, applies the earlier Givens
-//                  rotations, makes the new one and updates the implicit
-//                  residual (the paper's host-side least-squares step, moved
-//                  to the device so a cycle needs no host round trip).
+//   k_reduce_cols  sums h2.
+//   k_update_norm  w'' = w' - V h2 and the partial sums of ||w''||^2.
 // Every reduction is two-stage with a fixed summation order, so results are
 // bitwise reproducible run to run.
 #pragma once
@@ -43,6 +47,34 @@ struct XPlain {
   __device__ __forceinline__ T operator()(int c) const { return src[c]; }
 };
 
+// prod[i] = vals[p0 + i] * x(col[p0 + i]) for i < len (a tile staged in LDS).
+// The loads of SPMV_UNROLL nonzeros per thread are issued before their
+// gathers, and the gathers before the products, so a tile costs two memory
+// round trips per batch instead of one per nonzero.  Each product is rounded
+// on its own (no fused multiply-add with the row sum).
+template <typename T, typename XF>
+__device__ __forceinline__ void stage_products(const Csr& A, int p0, int len, const XF& xf, T* prod) {
+  const T* vals = (const T*)A.vals;
+  for (int i0 = 0; i0 < len; i0 += BLOCK * SPMV_UNROLL) {
+    int cc[SPMV_UNROLL];
+    T vv[SPMV_UNROLL], xv[SPMV_UNROLL];
+#pragma unroll
+    for (int k = 0; k < SPMV_UNROLL; ++k) {
+      const int i = i0 + (int)threadIdx.x + k * BLOCK;
+      const int ic = i < len ? i : len - 1;
+      cc[k] = A.col[p0 + ic];
+      vv[k] = vals[p0 + ic];
+    }
+#pragma unroll
+    for (int k = 0; k < SPMV_UNROLL; ++k) xv[k] = xf(cc[k]);
+#pragma unroll
+    for (int k = 0; k < SPMV_UNROLL; ++k) {
+      const int i = i0 + (int)threadIdx.x + k * BLOCK;
+      if (i < len) prod[i] = vv[k] * xv[k];
+    }
+  }
+}
+
 // Row-tiled CSR SpMV: a block takes a contiguous range of tiles; per tile the
 // nonzeros are streamed with coalesced loads, multiplied by the gathered x and
 // staged in LDS, then each thread sums one row in column order.  epi(r, y) is
@@ -58,10 +90,7 @@ __device__ __forceinline__ void spmv_tiles(const Csr& A, const XF& xf, EPI& epi,
     const int p0 = A.rowptr[r0], p1 = A.rowptr[r1];
     const int len = p1 - p0;
     if (len <= TILE_NNZ) {
-      for (int i = threadIdx.x; i < len; i += BLOCK) {
-        const int c = A.col[p0 + i];
-        prod[i] = vals[p0 + i] * xf(c);
-      }
+      stage_products<T>(A, p0, len, xf, prod);
       __syncthreads();
       for (int rr = threadIdx.x; rr < r1 - r0; rr += BLOCK) {
         const int r = r0 + rr;
@@ -171,6 +200,18 @@ struct QuadStore<double> {
   }
 };
 
+// 1 / ||w''|| of the previous iteration, the scale of the next basis vector:
+// summed from the partials k_update_norm left (nB > 0) in the order the
+// Givens step sums them (so both get the same bits), or read from the state
+// at a cycle start (nB == 0).  Called by every thread of the block.
+template <typename T>
+__device__ __forceinline__ T prev_inv_norm(const State& st, const T* norm_part, int nB) {
+  if (nB == 0) return (T)st.hdr->inv_h;
+  __shared__ T s_n[1];
+  reduce_partials(norm_part, 1, nB, s_n);
+  return T(1) / sqrt(s_n[0]);
+}
+
 // w = A v_j and the partial sums of h1 = V_{j+1}^T w.
 //
 // Per tile: the SpMV products are staged in LDS and summed per row (one
@@ -182,20 +223,21 @@ struct QuadStore<double> {
 // across the wave once at the end.  Columns c >= 4*SLOTS are left to k_dots.
 template <typename T, typename S, int SLOTS, bool SCALED>
 __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict__ src, S* __restrict__ V, long ldv,
-                                                     int j, T* __restrict__ w_out, State st,
-                                                     T* __restrict__ part) {
+                                                     int j, T* __restrict__ w_out, State st, T* __restrict__ part,
+                                                     const T* __restrict__ norm_part, int nB) {
   if (st.hdr->flags & F_DONE) return;
   constexpr int KMAX = NWAVES * SLOTS;
-  __shared__ T prod[TILE_NNZ];
+  T* prod = dyn_lds<T>();  // one entry per nonzero of the largest tile
   __shared__ T ys[TILE_ROWS];
   __shared__ T vs[TILE_ROWS];
   __shared__ T s_vals[KMAX];
   __shared__ T s_red[NWAVES];
   const T* vals = (const T*)A.vals;
-  const T inv = SCALED ? (T)st.hdr->inv_h : T(1);
+  const T inv = SCALED ? prev_inv_norm<T>(st, norm_part, nB) : T(1);
   const XScaled<T, S> xs{src, inv};
   const int C = (j + 1 < KMAX) ? j + 1 : KMAX;  // columns handled here
-  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   T acc[SLOTS];
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q) acc[q] = T(0);
@@ -208,10 +250,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict_
     const int len = p1 - p0;
     const int nrows = r1 - r0;
     if (len <= TILE_NNZ) {
-      for (int i = threadIdx.x; i < len; i += BLOCK) {
-        const int c = A.col[p0 + i];
-        prod[i] = vals[p0 + i] * (SCALED ? xs(c) : src[c]);
-      }
+      if (SCALED) stage_products<T>(A, p0, len, xs, prod);
+      else stage_products<T>(A, p0, len, XPlain<T>{src}, prod);
       __syncthreads();
       for (int rr = threadIdx.x; rr < nrows; rr += BLOCK) {
         const int r = r0 + rr;
@@ -318,77 +358,120 @@ __global__ __launch_bounds__(BLOCK) void k_dots(int n, const S* __restrict__ V, 
 // second kernel: first-pass update + second-pass projection
 // ---------------------------------------------------------------------------
 
-// Each lane owns two consecutive rows (8-byte loads for fp32).  Columns
-// c < KREG are held in registers between the update and the projection;
-// columns KREG <= c < k (k <= KACC) are loaded a second time (the rows were
-// just touched, so the reload is served by the caches).  Workspace vectors
-// and basis columns are padded to ldv rows, so the pair loads stay in bounds;
-// the padded row is masked out.
-template <typename T, typename S, int KREG, int KACC>
+// R consecutive rows of one column (R = 4, 2, 1; the first row a multiple of R).
+template <typename S, typename T, int R>
+struct Rows;
+template <typename S, typename T>
+struct Rows<S, T, 4> {
+  static __device__ __forceinline__ void load(const S* p, T (&v)[4]) { Quad<S, T>::load(p, v); }
+};
+template <typename S, typename T>
+struct Rows<S, T, 2> {
+  static __device__ __forceinline__ void load(const S* p, T (&v)[2]) { Pair<S, T>::load(p, v); }
+};
+template <typename S, typename T>
+struct Rows<S, T, 1> {
+  static __device__ __forceinline__ void load(const S* p, T (&v)[1]) { v[0] = Basis<S, T>::load(p); }
+};
+template <typename T, int R>
+__device__ __forceinline__ void store_rows(T* p, const T (&v)[R]) {
+  if constexpr (R == 4) QuadStore<T>::store(p, v);
+  else if constexpr (R == 2) Pair<T, T>::store(p, v);
+  else p[0] = v[0];
+}
+
+// The block's four waves share rows and split the columns: wave w holds
+// columns c = w + 4q (q < SLOTS) of R rows per lane in registers.  Per step of
+// 64 R rows: each wave forms its part of (V h1)[r] over its columns, the four
+// parts meet in LDS and are added in a fixed order, every wave computes
+// w' = w - V h1 for the step's rows, and then accumulates V[r, c] w'[r] for
+// its own columns from the registers.  So each V element is loaded once and
+// each lane keeps only SLOTS accumulators.  Workspace vectors and basis
+// columns are padded to ldv rows, so whole R-row loads stay in bounds; the
+// padded rows are masked to zero.
+template <typename T, typename S, int SLOTS, int R>
 __global__ __launch_bounds__(BLOCK) void k_update_proj(int n, const T* __restrict__ w_in, T* __restrict__ w_out,
                                                        const S* __restrict__ V, long ldv, int k, State st,
                                                        T* __restrict__ part) {
   if (st.hdr->flags & F_DONE) return;
-  __shared__ T s_h[KACC];
-  __shared__ T s_red[NWAVES * KACC];
-  __shared__ T s_vals[KACC];
-  for (int c = threadIdx.x; c < k; c += BLOCK) s_h[c] = (T)st.h1[c];
+  constexpr int KMAX = NWAVES * SLOTS;
+  constexpr int STEP = WAVE * R;
+  __shared__ T s_h[KMAX];
+  __shared__ T s_part[2][NWAVES][STEP];
+  __shared__ T s_vals[KMAX];
+  const double* h1 = st.h1_of(k - 1);
+  for (int c = threadIdx.x; c < KMAX; c += BLOCK) s_h[c] = c < k ? (T)h1[c] : T(0);
   __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);  // wave-uniform: hq in scalar registers
+  T hq[SLOTS], acc[SLOTS];
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) {
+    hq[q] = s_h[wid + NWAVES * q];
+    acc[q] = T(0);
+  }
   int r0, r1;
   block_rows(n, r0, r1);
-  T acc[KACC];
+  int buf = 0;
+  for (int base = r0; base < r1; base += STEP, buf ^= 1) {
+    const int r = base + R * lane;
+    const int nv = r1 - r;  // rows of this lane inside the block's range (may be <= 0 or > R)
+    T vr[SLOTS][R];
+    T s[R];
 #pragma unroll
-  for (int c = 0; c < KACC; ++c) acc[c] = T(0);
-  for (int r = r0 + 2 * threadIdx.x; r < r1; r += 2 * BLOCK) {
-    const bool two = r + 1 < r1;
-    T wv[2];
-    Pair<T, T>::load(w_in + r, wv);
-    if (!two) wv[1] = T(0);
-    T vr[KREG][2];
+    for (int i = 0; i < R; ++i) s[i] = T(0);
 #pragma unroll
-    for (int c = 0; c < KREG; ++c)
-      if (c < k) {
-        Pair<S, T>::load(V + (size_t)c * ldv + r, vr[c]);
-        if (!two) vr[c][1] = T(0);
+    for (int q = 0; q < SLOTS; ++q) {
+      const int c = wid + NWAVES * q;
+      if (c < k && nv > 0) {
+        Rows<S, T, R>::load(V + (size_t)c * ldv + r, vr[q]);
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+          if (i >= nv) vr[q][i] = T(0);
+      } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i) vr[q][i] = T(0);
       }
 #pragma unroll
-    for (int c = 0; c < KREG; ++c)
-      if (c < k) {
-        wv[0] -= s_h[c] * vr[c][0];
-        wv[1] -= s_h[c] * vr[c][1];
-      }
-#pragma unroll
-    for (int cb = KREG; cb < KACC; cb += 16) {
-#pragma unroll
-      for (int c = cb; c < cb + 16 && c < KACC; ++c)
-        if (c < k) {
-          T v[2];
-          Pair<S, T>::load(V + (size_t)c * ldv + r, v);
-          if (!two) v[1] = T(0);
-          wv[0] -= s_h[c] * v[0];
-          wv[1] -= s_h[c] * v[1];
-        }
-      asm volatile("" ::: "memory");
+      for (int i = 0; i < R; ++i) s[i] += hq[q] * vr[q][i];
     }
-    if (two) Pair<T, T>::store(w_out + r, wv);
-    else w_out[r] = wv[0];
 #pragma unroll
-    for (int c = 0; c < KREG; ++c)
-      if (c < k) acc[c] += vr[c][0] * wv[0] + vr[c][1] * wv[1];
+    for (int i = 0; i < R; ++i) s_part[buf][wid][R * lane + i] = s[i];
+    __syncthreads();
+    T wv[R];
+    if (nv > 0) {
+      Rows<T, T, R>::load(w_in + r, wv);
+    } else {
 #pragma unroll
-    for (int cb = KREG; cb < KACC; cb += 16) {
+      for (int i = 0; i < R; ++i) wv[i] = T(0);
+    }
 #pragma unroll
-      for (int c = cb; c < cb + 16 && c < KACC; ++c)
-        if (c < k) {
-          T v[2];
-          Pair<S, T>::load(V + (size_t)c * ldv + r, v);
-          if (!two) v[1] = T(0);
-          acc[c] += v[0] * wv[0] + v[1] * wv[1];
-        }
-      asm volatile("" ::: "memory");
+    for (int i = 0; i < R; ++i) {
+      const int e = R * lane + i;
+      const T t = (s_part[buf][0][e] + s_part[buf][1][e]) + (s_part[buf][2][e] + s_part[buf][3][e]);
+      wv[i] = (i < nv) ? wv[i] - t : T(0);
+    }
+    if (wid == 0 && nv > 0) {
+      if (nv >= R) {
+        store_rows<T, R>(w_out + r, wv);
+      } else {
+        for (int i = 0; i < nv; ++i) w_out[r + i] = wv[i];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q)
+#pragma unroll
+      for (int i = 0; i < R; ++i) acc[q] += vr[q][i] * wv[i];
+  }
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) {
+    const int c = wid + NWAVES * q;
+    if (c < k) {
+      const T v = wave_sum(acc[q]);
+      if (lane == 0) s_vals[c] = v;
     }
   }
-  block_reduce_vec(acc, k, s_red, s_vals);
+  __syncthreads();
   store_partials(s_vals, k, part);
 }
 
@@ -422,26 +505,27 @@ __global__ __launch_bounds__(BLOCK) void k_update(int n, const T* __restrict__ w
 // (thread 0) touches no global memory.
 template <typename T>
 __device__ __forceinline__ void givens_tail(const State& st, int j, int kmax, T nrm2, T* s_col, T* s_cs, T* s_sn) {
-  __shared__ T s_sq[NWAVES];
+  __shared__ T s_sq[16];
   __shared__ int s_flags;
   __shared__ T s_g[2];
   StateHdr* hd = st.hdr;
   const int ld = st.ld;
+  const double* h1 = st.h1_of(j);
   double* Hc = st.Hbar + (size_t)j * ld;
   double* Rc = st.R + (size_t)j * ld;
   T sq = T(0);
-  for (int i = threadIdx.x; i <= j; i += BLOCK) {
-    const T v = (T)st.h1[i] + (T)st.h2[i];
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    const T v = (T)h1[i] + (T)st.h2[i];
     Hc[i] = (double)v;
     s_col[i] = v;
     sq += v * v;
   }
-  for (int i = threadIdx.x; i < j; i += BLOCK) {
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
     s_cs[i] = (T)st.cs[i];
     s_sn[i] = (T)st.sn[i];
   }
   if (threadIdx.x == 0) s_g[0] = (T)st.g[j];
-  sq = block_sum(sq, s_sq);  // ends with a barrier
+  sq = block_sum_any(sq, s_sq);  // ends with a barrier
   if (threadIdx.x == 0) {
     const T hn = sqrt(nrm2);
     Hc[j + 1] = (double)hn;
@@ -490,9 +574,9 @@ __device__ __forceinline__ void givens_tail(const State& st, int j, int kmax, T 
   }
   __syncthreads();
   if (!(s_flags & F_NUMERIC))
-    for (int i = threadIdx.x; i <= j + 1; i += BLOCK) Rc[i] = (double)s_col[i];
+    for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) Rc[i] = (double)s_col[i];
   // keep both matrices clean below row j+1 (the workspace is not zeroed)
-  for (int i = j + 2 + threadIdx.x; i < ld; i += BLOCK) {
+  for (int i = j + 2 + threadIdx.x; i < ld; i += blockDim.x) {
     Hc[i] = 0.0;
     Rc[i] = 0.0;
   }
@@ -547,21 +631,48 @@ __global__ __launch_bounds__(BLOCK) void k_update_norm(int n, const T* __restric
 // one-block tail kernels of the cross-block reductions
 // ---------------------------------------------------------------------------
 
-// h[c] = sum of the partials of column c (c < nv); with last_to >= 0 the
-// last column goes to h[last_to] instead (the freshly formed basis vector).
+// h[c] = sum of the partials of column c < nv.  Grid ceil(nv / 4): wave w
+// of block b sums column 4 b + w, so the partials are read by many CUs at
+// once (one CU alone is latency bound on them).
 template <typename T>
-__global__ __launch_bounds__(512) void k_reduce_h(const T* __restrict__ part, int nv, int B, double* h, int last_to,
-                                                   State st, int check_done) {
+__global__ __launch_bounds__(BLOCK) void k_reduce_cols(const T* __restrict__ part, int nv, int B, double* h, State st,
+                                                       int check_done) {
   if (check_done && (st.hdr->flags & F_DONE)) return;
-  __shared__ T s_out[MAX_RESTART + 2];
-  reduce_partials(part, nv, B, s_out);
-  for (int c = threadIdx.x; c < nv; c += blockDim.x) {
-    const int idx = (last_to >= 0 && c == nv - 1) ? last_to : c;
-    h[idx] = (double)s_out[c];
-  }
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int c = blockIdx.x * NWAVES + wid;
+  if (c >= nv) return;
+  const T v = wave_reduce_column(part + (size_t)c * MAX_BLOCKS, B);
+  if ((threadIdx.x & (WAVE - 1)) == 0) h[c] = (double)v;
 }
 
-// ||w''||^2 from the partials of k_update_norm, then the Givens update.
+// Blocks 0 .. ceil(nv/4)-1: h1 of iteration jg + 1 from the partials of
+// k_spmv_proj, as k_reduce_cols.  For jg >= 0 one more block makes the Givens
+// step of iteration jg from the ||w''||^2 partials of its k_update_norm (it
+// reads the other h1 buffer, so both run at once).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_reduce_h1_givens(const T* __restrict__ part, int nv, int B,
+                                                            const T* __restrict__ norm_part, int nB, State st, int jg,
+                                                            int kmax) {
+  if (st.hdr->flags & F_DONE) return;
+  const int ncb = (nv + NWAVES - 1) / NWAVES;
+  if ((int)blockIdx.x < ncb) {
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int c = blockIdx.x * NWAVES + wid;
+    if (c >= nv) return;
+    const T v = wave_reduce_column(part + (size_t)c * MAX_BLOCKS, B);
+    if ((threadIdx.x & (WAVE - 1)) == 0) st.h1_of(jg + 1)[c] = (double)v;
+    return;
+  }
+  __shared__ T s_n[1];
+  __shared__ T s_col[MAX_RESTART + 2];
+  __shared__ T s_cs[MAX_RESTART];
+  __shared__ T s_sn[MAX_RESTART];
+  reduce_partials(norm_part, 1, nB, s_n);
+  givens_tail<T>(st, jg, kmax, s_n[0], s_col, s_cs, s_sn);
+}
+
+// ||w''||^2 from the partials of k_update_norm, then the Givens update (the
+// last iteration of a cycle).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_norm_givens(const T* __restrict__ part, int B, State st, int j, int kmax) {
   if (st.hdr->flags & F_DONE) return;
@@ -586,7 +697,7 @@ __global__ __launch_bounds__(BLOCK) void k_sqrt_tail(const double* __restrict__ 
 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_backsolve(State st) {
-  extern __shared__ unsigned char s_dyn[];
+  unsigned char* s_dyn = dyn_lds<unsigned char>();
   const int flags = st.hdr->flags;
   const int k = st.hdr->k;
   if (threadIdx.x == 0) {
@@ -638,7 +749,7 @@ __global__ void k_init_state(State st, double rtol, int check_mode, double gamma
     hd->flags = 0;
     hd->cycle_k = 0;
     hd->cycle_flags = 0;
-    for (int i = 0; i < 8; ++i) hd->counter[i] = 0u;
+    for (int i = 0; i < 8; ++i) hd->spare[i] = 0u;
   }
 }
 
@@ -669,7 +780,7 @@ struct ResidEpi {
 // r = b - A x (fp64 matrix and vectors), gamma = ||r||_2 (Algorithm 2, first and last lines).
 __global__ __launch_bounds__(BLOCK) void k_resid64(Csr A, const double* __restrict__ x, const double* __restrict__ b,
                                                    double* __restrict__ r, double* __restrict__ part) {
-  __shared__ double prod[TILE_NNZ];
+  double* prod = dyn_lds<double>();  // one entry per nonzero of the largest tile
   __shared__ double s_vals[1], s_scr[NWAVES * WAVE];
   ResidEpi epi{b, r, 0.0};
   spmv_tiles<double>(A, XPlain<double>{x}, epi, prod, s_scr);
@@ -739,7 +850,7 @@ struct InnerResidEpi {
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_inner_resid(Csr A, const T* __restrict__ u, const T* __restrict__ rhat,
                                                        T* __restrict__ wtmp, T* __restrict__ part) {
-  __shared__ T prod[TILE_NNZ];
+  T* prod = dyn_lds<T>();  // one entry per nonzero of the largest tile
   __shared__ T s_vals[1], s_scr[NWAVES * WAVE];
   InnerResidEpi<T> epi{rhat, wtmp, T(0)};
   spmv_tiles<T>(A, XPlain<T>{u}, epi, prod, s_scr);
@@ -869,13 +980,13 @@ template <typename T, typename S, bool SCALED>
 __global__ __launch_bounds__(BLOCK) void k_poly_step(Csr A, const T* __restrict__ src, S* __restrict__ V, long ldv,
                                                      int j, int write_v, const T* __restrict__ W, int w_scaled,
                                                      T* __restrict__ Y, T* __restrict__ D, PolyCoef<T> cf, State st,
-                                                     int check_done) {
+                                                     int check_done, const T* __restrict__ norm_part, int nB) {
   if (check_done && (st.hdr->flags & F_DONE)) return;
-  __shared__ T prod[TILE_NNZ];
+  T* prod = dyn_lds<T>();  // one entry per nonzero of the largest tile
   __shared__ T s_scr[NWAVES * WAVE];
   PolyEpi<T, S, SCALED> epi;
   epi.src = src;
-  epi.inv = (T)st.hdr->inv_h;
+  epi.inv = (SCALED || w_scaled) ? prev_inv_norm<T>(st, norm_part, nB) : T(1);
   epi.V = V;
   epi.ldv = ldv;
   epi.j = j;
@@ -903,7 +1014,7 @@ struct PlainEpi {
 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_spmv(Csr A, const T* __restrict__ x, T* __restrict__ y) {
-  __shared__ T prod[TILE_NNZ];
+  T* prod = dyn_lds<T>();  // one entry per nonzero of the largest tile
   __shared__ T s_scr[NWAVES * WAVE];
   PlainEpi<T> epi{y};
   spmv_tiles<T>(A, XPlain<T>{x}, epi, prod, s_scr);
