@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--max-iters", type=int, default=1_000_000,
+                    help="cap on inner iterations of the timed solves (short hardware-counter runs only)")
     ap.add_argument("--suite", action="store_true",
                     help="also time the other workloads (150^3 anisotropic + polynomial, 128^3 27-point "
                          "bf16/fp32/fp64, 64^2 parity system); one JSON line each, after the main line")
@@ -126,7 +128,8 @@ def main():
     b = torch.from_numpy(system.b).cuda()
     x = torch.zeros_like(b)
     ws = B.Workspace()
-    p_ir = B.make_params(restart=args.restart, inner="fp32", basis=args.basis, rtol=1e-10, check_mode=1)
+    p_ir = B.make_params(restart=args.restart, inner="fp32", basis=args.basis, rtol=1e-10, check_mode=1,
+                         max_iters=args.max_iters)
     p_64 = B.make_params(restart=args.restart, inner="fp64", rtol=1e-10, check_mode=1)
 
     def run(p):
