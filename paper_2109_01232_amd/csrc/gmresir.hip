@@ -6,6 +6,7 @@
 // the back substitution, the fp64 correction and the fp64 residual -- and
 // the host reads the small state header once per refinement to decide on
 // convergence (the paper's restart-time check).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
@@ -205,7 +206,7 @@ State state_of(char* ws, const Layout& L) {
 }
 
 // ---------------------------------------------------------------------------
-// profiling (HIP events around every launch) and algorithmic byte counts
+// profiling (start/end events of every launch) and algorithmic byte counts
 // ---------------------------------------------------------------------------
 
 struct Prof {
@@ -225,18 +226,19 @@ struct Prof {
     }
     return pool[used++];
   }
-  template <typename F>
-  void run(int cat, double b, F&& launch) {
+  // Launch kern on strm and book it under category cat with b algorithmic
+  // bytes; when profiling, the kernel's own start and end are recorded
+  // (hipExtLaunchKernel events, no extra packets between kernels).
+  template <typename K, typename... Args>
+  void launch(int cat, double b, K kern, dim3 grid, dim3 block, size_t smem, hipStream_t strm, Args... args) {
     bytes[cat] += b;
     launches[cat] += 1;
     if (!on) {
-      launch();
+      hipLaunchKernelGGL(kern, grid, block, smem, strm, args...);
       return;
     }
     hipEvent_t e0 = take(), e1 = take();
-    if (e0) (void)hipEventRecord(e0, stream);
-    launch();
-    if (e1) (void)hipEventRecord(e1, stream);
+    hipExtLaunchKernelGGL(kern, grid, block, (std::uint32_t)smem, strm, e0, e1, 0u, args...);
     if (e0 && e1) pending.push_back({cat, {e0, e1}});
   }
   // after a stream synchronisation
@@ -432,17 +434,11 @@ struct Ctx {
       if (scaled && ps.x == PB_SRC) {
         auto kern = k_poly_step<T, S, true>;
         int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
-        prof->run(cat, b, [&] {
-          hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, write_v, W, w_scaled, y_out, D,
-                             cf, st, check_done, (const T*)norm_part(), nB);
-        });
+        prof->launch(cat, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, write_v, W, w_scaled, y_out, D, cf, st, check_done, (const T*)norm_part(), nB);
       } else {
         auto kern = k_poly_step<T, S, false>;
         int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
-        prof->run(cat, b, [&] {
-          hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, 0, W, w_scaled, y_out, D, cf,
-                             st, check_done, (const T*)norm_part(), nB);
-        });
+        prof->launch(cat, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, 0, W, w_scaled, y_out, D, cf, st, check_done, (const T*)norm_part(), nB);
       }
     }
   }
@@ -463,24 +459,16 @@ struct Ctx {
     // basis columns read from memory: all handled columns but the new one (SCALED)
     const int nread = SCALED ? std::min(j, C) : C;
     double b = spmv_bytes() + sT() * n * 2 + sS() * n * nread + (SCALED ? sS() * n : 0.0);
-    prof->run(GMRESIR_CAT_SPMV_PROJ, b, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, src, V, L.ldv, j, w1, st, part,
-                         (const T*)norm_part(), nB);
-    });
+    prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, src, V, L.ldv, j, w1, st, part, (const T*)norm_part(), nB);
     auto tail = k_reduce_h1_givens<T>;
     const int tg = (C + NWAVES - 1) / NWAVES + (j > 0 ? 1 : 0);
-    prof->run(GMRESIR_CAT_TAIL, 0.0, [&] {
-      hipLaunchKernelGGL(tail, dim3(tg), dim3(BLOCK), 0, stream, (const T*)part, C, g, (const T*)norm_part(), nB, st,
-                         j - 1, kmax);
-    });
+    prof->launch(GMRESIR_CAT_TAIL, 0.0, tail, dim3(tg), dim3(BLOCK), 0, stream, (const T*)part, C, g, (const T*)norm_part(), nB, st, j - 1, kmax);
   }
 
   void reduce_h(int cat, int producer_grid, int nv, double* h) {
     auto kern = k_reduce_cols<T>;
     const int tg = (nv + NWAVES - 1) / NWAVES;
-    prof->run(cat == GMRESIR_CAT_OTHER ? cat : GMRESIR_CAT_TAIL, 0.0, [&] {
-      hipLaunchKernelGGL(kern, dim3(tg), dim3(BLOCK), 0, stream, (const T*)part, nv, producer_grid, h, st, 1);
-    });
+    prof->launch(cat == GMRESIR_CAT_OTHER ? cat : GMRESIR_CAT_TAIL, 0.0, kern, dim3(tg), dim3(BLOCK), 0, stream, (const T*)part, nv, producer_grid, h, st, 1);
   }
 
   template <bool SCALED>
@@ -497,9 +485,7 @@ struct Ctx {
   void dots(int c0, int nc, const T* w, double* h, int cat) {
     auto kern = k_dots<T, S>;
     int g = grid_rows((const void*)kern, n);
-    prof->run(cat, sS() * n * nc + sT() * n, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, V, L.ldv, c0, nc, w, st, 1, part);
-    });
+    prof->launch(cat, sS() * n * nc + sT() * n, kern, dim3(g), dim3(BLOCK), 0, stream, n, V, L.ldv, c0, nc, w, st, 1, part);
     reduce_h(cat, g, nc, h + c0);
   }
 
@@ -507,9 +493,7 @@ struct Ctx {
   void launch_update_proj(int k) {
     auto kern = k_update_proj<T, S, SLOTS, R>;
     int g = grid_rows((const void*)kern, n);
-    prof->run(GMRESIR_CAT_UPDATE_PROJ, sT() * n * 2 + sS() * n * k, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w1, w2, V, L.ldv, k, st, part);
-    });
+    prof->launch(GMRESIR_CAT_UPDATE_PROJ, sT() * n * 2 + sS() * n * k, kern, dim3(g), dim3(BLOCK), 0, stream, n, w1, w2, V, L.ldv, k, st, part);
     reduce_h(GMRESIR_CAT_UPDATE_PROJ, g, k, st.h2);
   }
 
@@ -526,10 +510,7 @@ struct Ctx {
     else {
       auto kern = k_update<T, S>;
       int g = grid_rows((const void*)kern, n);
-      prof->run(GMRESIR_CAT_OTHER, sT() * n * 2 + sS() * n * k, [&] {
-        hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w1, w2, V, L.ldv, k, (const double*)st.h1_of(k - 1),
-                           st);
-      });
+      prof->launch(GMRESIR_CAT_OTHER, sT() * n * 2 + sS() * n * k, kern, dim3(g), dim3(BLOCK), 0, stream, n, w1, w2, V, L.ldv, k, (const double*)st.h1_of(k - 1), st);
       for (int c0 = 0; c0 < k; c0 += 64) dots(c0, std::min(64, k - c0), w2, st.h2, GMRESIR_CAT_OTHER);
     }
   }
@@ -537,18 +518,14 @@ struct Ctx {
   void update_norm(int j) {
     auto kern = k_update_norm<T, S>;
     int g = grid_rows((const void*)kern, n);
-    prof->run(GMRESIR_CAT_UPDATE_NORM, sT() * n * 2 + sS() * n * (j + 1), [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, w2, wtmp, V, L.ldv, j, st, norm_part());
-    });
+    prof->launch(GMRESIR_CAT_UPDATE_NORM, sT() * n * 2 + sS() * n * (j + 1), kern, dim3(g), dim3(BLOCK), 0, stream, n, w2, wtmp, V, L.ldv, j, st, norm_part());
   }
 
   // Givens step of the last iteration of a cycle (the others run in the
   // tail after the next iteration's SpMV)
   void norm_givens(int j, int kmax) {
     auto tail = k_norm_givens<T>;
-    prof->run(GMRESIR_CAT_TAIL, 0.0, [&] {
-      hipLaunchKernelGGL(tail, dim3(1), dim3(BLOCK), 0, stream, (const T*)norm_part(), norm_grid(), st, j, kmax);
-    });
+    prof->launch(GMRESIR_CAT_TAIL, 0.0, tail, dim3(1), dim3(BLOCK), 0, stream, (const T*)norm_part(), norm_grid(), st, j, kmax);
   }
 
   // one inner iteration j of a cycle of at most kmax steps
@@ -574,95 +551,71 @@ struct Ctx {
     auto kern = k_backsolve<T>;
     size_t tri = (size_t)kmax * (kmax + 1) / 2 * sizeof(T);
     size_t smem = (size_t)(((kmax + 1) & ~1) + 2) * sizeof(T) + std::min<size_t>(40960, tri);
-    prof->run(GMRESIR_CAT_REFINE, 0.0, [&] {
-      hipLaunchKernelGGL(kern, dim3(1), dim3(BLOCK), smem, stream, st);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, 0.0, kern, dim3(1), dim3(BLOCK), smem, stream, st);
   }
 
   void init(double rtol, int check_mode, double gamma0) {
-    prof->run(GMRESIR_CAT_REFINE, 0.0, [&] {
-      hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, stream, st, rtol, check_mode, gamma0);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, 0.0, k_init_state, dim3(1), dim3(64), 0, stream, st, rtol, check_mode, gamma0);
   }
 
   void norm64(const double* v, double* dst) {
     auto kern = k_norm64;
     int g = grid_rows((const void*)kern, n);
-    prof->run(GMRESIR_CAT_REFINE, 8.0 * n, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, v, (double*)part);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, 8.0 * n, kern, dim3(g), dim3(BLOCK), 0, stream, n, v, (double*)part);
     sqrt_tail(g, dst);
   }
 
   void sqrt_tail(int producer_grid, double* dst) {
-    prof->run(GMRESIR_CAT_REFINE, 0.0, [&] {
-      hipLaunchKernelGGL(k_sqrt_tail, dim3(1), dim3(BLOCK), 0, stream, (const double*)part, producer_grid, dst);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, 0.0, k_sqrt_tail, dim3(1), dim3(BLOCK), 0, stream, (const double*)part, producer_grid, dst);
   }
 
   void cycle_tail(int producer_grid) {
     auto kern = k_cycle_tail<T>;
-    prof->run(GMRESIR_CAT_REFINE, 0.0, [&] {
-      hipLaunchKernelGGL(kern, dim3(1), dim3(BLOCK), 0, stream, (const T*)part, producer_grid, st);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, 0.0, kern, dim3(1), dim3(BLOCK), 0, stream, (const T*)part, producer_grid, st);
   }
 
   void resid64(const double* x, const double* b) {
     auto kern = k_resid64;
     int g = grid_tiles((const void*)kern, A64.ntiles, lds_64());
-    prof->run(GMRESIR_CAT_REFINE, 12.0 * A->nnz + 4.0 * (A->n + 1) + 8.0 * n * 3, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), lds_64(), stream, A64, x, b, r64, (double*)part);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, 12.0 * A->nnz + 4.0 * (A->n + 1) + 8.0 * n * 3, kern, dim3(g), dim3(BLOCK), lds_64(), stream, A64, x, b, r64, (double*)part);
     sqrt_tail(g, &st.hdr->gamma);
   }
 
   void cast(const double* r) {
     auto kern = k_cast<T>;
     int g = grid_rows((const void*)kern, n);
-    prof->run(GMRESIR_CAT_REFINE, 8.0 * n + sT() * n * (rhat ? 2 : 1), [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, r, wtmp, rhat, st, part);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, 8.0 * n + sT() * n * (rhat ? 2 : 1), kern, dim3(g), dim3(BLOCK), 0, stream, n, r, wtmp, rhat, st, part);
     cycle_tail(g);
   }
 
   void correct_x(double* x, int kmax) {
     auto kern = k_correct_x<T, S>;
     int g = grid_rows((const void*)kern, n);
-    prof->run(GMRESIR_CAT_REFINE, sS() * n * kmax + 16.0 * n, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, V, L.ldv, st, x);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, sS() * n * kmax + 16.0 * n, kern, dim3(g), dim3(BLOCK), 0, stream, n, V, L.ldv, st, x);
   }
 
   void vy(T* out, int kmax) {
     auto kern = k_vy<T, S>;
     int g = grid_rows((const void*)kern, n);
-    prof->run(GMRESIR_CAT_REFINE, sS() * n * kmax + sT() * n, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, V, L.ldv, st, out);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, sS() * n * kmax + sT() * n, kern, dim3(g), dim3(BLOCK), 0, stream, n, V, L.ldv, st, out);
   }
 
   void accum(const T* zz, T* uu, int first) {
     auto kern = k_accum<T>;
     int g = grid_rows((const void*)kern, n);
-    prof->run(GMRESIR_CAT_REFINE, sT() * n * (first ? 2 : 3), [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, zz, uu, first);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, sT() * n * (first ? 2 : 3), kern, dim3(g), dim3(BLOCK), 0, stream, n, zz, uu, first);
   }
 
   void axpy_x(const T* uu, double* x) {
     auto kern = k_axpy_x<T>;
     int g = grid_rows((const void*)kern, n);
-    prof->run(GMRESIR_CAT_REFINE, sT() * n + 16.0 * n, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, stream, n, uu, st, x);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, sT() * n + 16.0 * n, kern, dim3(g), dim3(BLOCK), 0, stream, n, uu, st, x);
   }
 
   void inner_resid() {
     auto kern = k_inner_resid<T>;
     int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
-    prof->run(GMRESIR_CAT_REFINE, spmv_bytes() + sT() * n * 3, [&] {
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, (const T*)u, (const T*)rhat, wtmp, part);
-    });
+    prof->launch(GMRESIR_CAT_REFINE, spmv_bytes() + sT() * n * 3, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, (const T*)u, (const T*)rhat, wtmp, part);
     cycle_tail(g);
   }
 
