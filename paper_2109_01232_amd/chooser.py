@@ -252,6 +252,11 @@ def cmd_evaluate(args):
         r, total, cfg = solve_with_chooser(R, chooser)
         rec = {"seed": seed, "n": sysm.A.n, "default": base, "chosen": list(cfg), "chosen_run": r,
                "chosen_total": total, "speedup": (base["time"] / total) if base["ok"] else None}
+        for fixed in args.also:
+            fc = tuple(int(v) for v in fixed.split(","))
+            fr = R.run(fc)
+            ft = fr["time"] if fr["ok"] else fr["time"] + base["time"]
+            rec["fixed_" + fixed] = {"run": fr, "speedup": (base["time"] / ft) if base["ok"] else None}
         out.append(rec)
         print(f"[eval] seed {seed} n={sysm.A.n} default {base['time']:.4f}s chosen {cfg} {total:.4f}s "
               f"ok={r['ok']} speedup={rec['speedup']}", flush=True)
@@ -260,9 +265,14 @@ def cmd_evaluate(args):
             f.write(json.dumps(rec) + "\n")
     sp = np.array([r["speedup"] for r in out if r["speedup"] is not None])
     if len(sp):
-        print(json.dumps({"systems": len(sp), "geomean_speedup": float(np.exp(np.log(sp).mean())),
-                          "median_speedup": float(np.median(sp)), "frac_improved": float(np.mean(sp > 1.0)),
-                          "worst": float(sp.min()), "best": float(sp.max())}), flush=True)
+        summary = {"systems": len(sp), "geomean_speedup": float(np.exp(np.log(sp).mean())),
+                   "median_speedup": float(np.median(sp)), "frac_improved": float(np.mean(sp > 1.0)),
+                   "worst": float(sp.min()), "best": float(sp.max()),
+                   "fallbacks": int(sum(1 for r in out if not r["chosen_run"]["ok"]))}
+        for fixed in args.also:
+            fs = np.array([r["fixed_" + fixed]["speedup"] for r in out if r["fixed_" + fixed]["speedup"]])
+            summary["fixed_" + fixed + "_geomean_speedup"] = float(np.exp(np.log(fs).mean()))
+        print(json.dumps(summary), flush=True)
 
 
 def main(argv=None):
@@ -287,6 +297,7 @@ def main(argv=None):
     e.add_argument("--stop", type=int, default=2000)
     e.add_argument("--n-max", type=float, default=2e6)
     e.add_argument("--out", required=True)
+    e.add_argument("--also", nargs="*", default=[], help="fixed configurations m,cap,deg timed beside, e.g. 50,1,10")
     args = ap.parse_args(argv)
     {"sweep": cmd_sweep, "train": cmd_train, "evaluate": cmd_evaluate}[args.cmd](args)
 

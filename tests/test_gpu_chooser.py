@@ -1,0 +1,89 @@
+"""The trained parameter chooser on the GPU: its network agrees with the
+oracle network on the committed weights, and on held-out systems (seeds the
+training never saw) the configurations it picks cost less than the fixed
+defaults (m = 50, one cycle per refinement, no polynomial).
+
+The gain is measured deterministically: each solve's inner iteration count
+(solves are bitwise reproducible) times the per-iteration byte model of the
+sweep, plus the polynomial set-up's SpMVs; every accepted solve reaches the
+fp64 target 1e-10 (a configuration that does not is charged its work and
+replaced by the default, as ``solve_with_chooser`` does).  Wall times of the
+full 200-system evaluation are recorded beside the weights.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mlp as OM
+from paper_2109_01232_amd import binding as B
+from paper_2109_01232_amd import chooser as C
+from paper_2109_01232_amd import problems as P
+
+from gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+HELD_OUT = list(range(1800, 1816))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(C.WEIGHTS_PATH):
+        pytest.skip("no trained chooser weights committed")
+    B.lib()
+
+
+@pytest.fixture(scope="module")
+def chooser():
+    return C.Chooser.load()
+
+
+def modeled_cost(cfg, iters, n, nnz):
+    m, capm, deg = cfg
+    setup = (deg + 1) * (8.0 * nnz + 12.0 * n + 4.0 * n * (deg + 2)) if deg > 0 else 0.0
+    return iters * C._iter_cost(cfg, n, nnz) + setup
+
+
+def test_network_matches_oracle_on_committed_weights(chooser):
+    import json
+
+    with open(C.WEIGHTS_PATH) as f:
+        w = json.load(f)
+    X = np.random.default_rng(0).standard_normal((40, 16)) * 2.0
+    say("chooser forward parity")
+    got = chooser.predict_raw(X)
+    c = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    ref = OM.forward(c(w["params"]), c(X), c(w["shift"]), c(w["scale"]))
+    assert np.max(np.abs(got - ref)) <= 1e-4 * max(1.0, np.abs(ref).max())
+
+
+def test_chooser_beats_defaults_on_held_out_systems(chooser):
+    ratios = []
+    for seed in HELD_OUT:
+        sysm = P.chooser_system(seed)
+        say("chooser held-out system", seed, sysm.A.n)
+        R = C.Runner(sysm)
+        n, nnz = sysm.A.n, sysm.A.nnz
+        base = R.run(C.DEFAULT)
+        assert base["ok"], seed
+        cfg = chooser.choose(R.features())
+        assert cfg in C.grid()
+        r = R.run(cfg)
+        cost = modeled_cost(cfg, r["iters"], n, nnz)
+        if not r["ok"]:
+            cost += modeled_cost(C.DEFAULT, base["iters"], n, nnz)
+        else:
+            assert r["resid"] <= C.RTOL
+        ratios.append(cost / modeled_cost(C.DEFAULT, base["iters"], n, nnz))
+        del R
+    ratios = np.array(ratios)
+    geo = float(np.exp(np.log(ratios).mean()))
+    say("chooser cost ratio geomean", geo, "per system", np.round(ratios, 3).tolist())
+    assert geo < 0.8
+    assert np.mean(ratios < 1.0) >= 0.75
