@@ -93,7 +93,14 @@ int grid_rows(const void* kern, int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, want));
 }
 
-int grid_tiles(const void* kern, int ntiles, size_t smem) {
+// Plain SpMV kernels take one tile per block (blocks beyond the resident ones
+// start as others finish, which balances tiles of unequal cost: measured 4.4
+// vs 3.7 TB/s on the 7-point 150^3 polynomial steps).  Kernels that leave
+// per-block partial sums run one resident wave of blocks (at most MAX_GRID),
+// each over a contiguous range of tiles, which amortises their prologue and
+// partial sums (one tile per block measured 17 % slower there).
+int grid_tiles(int ntiles) { return std::max(1, ntiles); }
+int grid_tiles_part(const void* kern, int ntiles, size_t smem) {
   return std::max(1, std::min(resident_grid(kern, smem), ntiles));
 }
 
@@ -213,11 +220,25 @@ struct Prof {
   bool on = false;
   hipStream_t stream = nullptr;
   std::vector<hipEvent_t> pool;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
   size_t used = 0;
   double t[GMRESIR_NCAT] = {0};
   double bytes[GMRESIR_NCAT] = {0};
   int64_t launches[GMRESIR_NCAT] = {0};
+  // Launches since the last commit.  Kernels of iteration j (tag = j) after
+  // the step where a cycle stopped exit at once without work; they are not
+  // booked.  "early" kernels of an iteration (polynomial steps, SpMV +
+  // projection, the h1/Givens tail) still run in the iteration right after
+  // the stop, because the stop is decided by that tail.
+  struct Entry {
+    int cat;
+    double b;
+    int tag;
+    bool early;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Entry> pend;
+  int tag = -1;
+  bool early = false;
   hipEvent_t take() {
     if (used == pool.size()) {
       hipEvent_t e;
@@ -231,23 +252,28 @@ struct Prof {
   // (hipExtLaunchKernel events, no extra packets between kernels).
   template <typename K, typename... Args>
   void launch(int cat, double b, K kern, dim3 grid, dim3 block, size_t smem, hipStream_t strm, Args... args) {
-    bytes[cat] += b;
-    launches[cat] += 1;
+    Entry e{cat, b, tag, early, nullptr, nullptr};
     if (!on) {
       hipLaunchKernelGGL(kern, grid, block, smem, strm, args...);
-      return;
+    } else {
+      e.e0 = take();
+      e.e1 = take();
+      hipExtLaunchKernelGGL(kern, grid, block, (std::uint32_t)smem, strm, e.e0, e.e1, 0u, args...);
     }
-    hipEvent_t e0 = take(), e1 = take();
-    hipExtLaunchKernelGGL(kern, grid, block, (std::uint32_t)smem, strm, e0, e1, 0u, args...);
-    if (e0 && e1) pending.push_back({cat, {e0, e1}});
+    pend.push_back(e);
   }
-  // after a stream synchronisation
-  void flush() {
-    for (auto& p : pending) {
+  // After a stream synchronisation: book the pending launches; k = steps the
+  // cycle among them completed.
+  void commit(int k) {
+    for (const Entry& e : pend) {
+      const bool ran = e.tag < 0 || e.tag < k || (e.tag == k && e.early);
+      if (!ran) continue;
+      bytes[e.cat] += e.b;
+      launches[e.cat] += 1;
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) t[p.first] += ms * 1e-3;
+      if (e.e0 && e.e1 && hipEventElapsedTime(&ms, e.e0, e.e1) == hipSuccess) t[e.cat] += ms * 1e-3;
     }
-    pending.clear();
+    pend.clear();
     used = 0;
   }
   ~Prof() {
@@ -433,11 +459,11 @@ struct Ctx {
                  (write_v ? sS() * n : 0.0);
       if (scaled && ps.x == PB_SRC) {
         auto kern = k_poly_step<T, S, true>;
-        int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
+        int g = grid_tiles(Ain.ntiles);
         prof->launch(cat, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, write_v, W, w_scaled, y_out, D, cf, st, check_done, (const T*)norm_part(), nB);
       } else {
         auto kern = k_poly_step<T, S, false>;
-        int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
+        int g = grid_tiles(Ain.ntiles);
         prof->launch(cat, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, 0, W, w_scaled, y_out, D, cf, st, check_done, (const T*)norm_part(), nB);
       }
     }
@@ -454,7 +480,7 @@ struct Ctx {
   void launch_spmv_proj(const T* src, int j, int kmax, int nB) {
     constexpr int KMAX = NWAVES * SLOTS;
     auto kern = k_spmv_proj<T, S, SLOTS, SCALED>;
-    int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
+    int g = grid_tiles_part((const void*)kern, Ain.ntiles, lds_in());
     const int C = std::min(j + 1, KMAX);
     // basis columns read from memory: all handled columns but the new one (SCALED)
     const int nread = SCALED ? std::min(j, C) : C;
@@ -478,7 +504,9 @@ struct Ctx {
     else if (k <= 32) launch_spmv_proj<8, SCALED>(src, j, kmax, nB);
     else if (k <= 64) launch_spmv_proj<16, SCALED>(src, j, kmax, nB);
     else launch_spmv_proj<32, SCALED>(src, j, kmax, nB);
-    // columns beyond the fused limit (V[:, j] is in memory by now)
+    // columns beyond the fused limit (V[:, j] is in memory by now); they
+    // skip when the tail has just stopped the cycle
+    prof->early = false;
     for (int c0 = 128; c0 < k; c0 += 64) dots(c0, std::min(64, k - c0), w1, st.h1_of(j), GMRESIR_CAT_OTHER);
   }
 
@@ -531,12 +559,15 @@ struct Ctx {
   // one inner iteration j of a cycle of at most kmax steps
   void iteration(int j, int kmax) {
     const int nB = j > 0 ? norm_grid() : 0;
+    prof->tag = j;
+    prof->early = true;
     if (poly_on) {
       run_poly(wtmp, true, j, z, 1, GMRESIR_CAT_POLY, nB);
       spmv_proj_dispatch<false>(z, j, kmax, nB);
     } else {
       spmv_proj_dispatch<true>(wtmp, j, kmax, nB);
     }
+    prof->early = false;
     update_proj_dispatch(j + 1);
     update_norm(j);
   }
@@ -544,7 +575,10 @@ struct Ctx {
   // the Arnoldi steps of one cycle, ending with its last Givens step
   void cycle(int kmax) {
     for (int j = 0; j < kmax; ++j) iteration(j, kmax);
+    prof->tag = kmax - 1;
+    prof->early = false;
     norm_givens(kmax - 1, kmax);
+    prof->tag = -1;
   }
 
   void backsolve(int kmax) {
@@ -576,7 +610,7 @@ struct Ctx {
 
   void resid64(const double* x, const double* b) {
     auto kern = k_resid64;
-    int g = grid_tiles((const void*)kern, A64.ntiles, lds_64());
+    int g = grid_tiles_part((const void*)kern, A64.ntiles, lds_64());
     prof->launch(GMRESIR_CAT_REFINE, 12.0 * A->nnz + 4.0 * (A->n + 1) + 8.0 * n * 3, kern, dim3(g), dim3(BLOCK), lds_64(), stream, A64, x, b, r64, (double*)part);
     sqrt_tail(g, &st.hdr->gamma);
   }
@@ -614,7 +648,7 @@ struct Ctx {
 
   void inner_resid() {
     auto kern = k_inner_resid<T>;
-    int g = grid_tiles((const void*)kern, Ain.ntiles, lds_in());
+    int g = grid_tiles_part((const void*)kern, Ain.ntiles, lds_in());
     prof->launch(GMRESIR_CAT_REFINE, spmv_bytes() + sT() * n * 3, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, (const T*)u, (const T*)rhat, wtmp, part);
     cycle_tail(g);
   }
@@ -623,7 +657,7 @@ struct Ctx {
     HIP_TRY(hipMemcpyAsync(h, st.hdr, sizeof(StateHdr), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     HIP_TRY(hipGetLastError());
-    prof->flush();
+    prof->commit(h->cycle_k);
     return 0;
   }
 };
@@ -953,12 +987,12 @@ int gmresir_spmv(const gmresir_matrix* A, int32_t prec, const void* x, void* y, 
   if (prec == GMRESIR_FP64) {
     auto kern = k_spmv<double>;
     const size_t smem = (size_t)A->lds_nnz * sizeof(double);
-    int g = grid_tiles((const void*)kern, A->ntiles, smem);
+    int g = grid_tiles(A->ntiles);
     hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), smem, s, csr_of(A, true), (const double*)x, (double*)y);
   } else if (prec == GMRESIR_FP32) {
     auto kern = k_spmv<float>;
     const size_t smem = (size_t)A->lds_nnz * sizeof(float);
-    int g = grid_tiles((const void*)kern, A->ntiles, smem);
+    int g = grid_tiles(A->ntiles);
     hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), smem, s, csr_of(A, false), (const float*)x, (float*)y);
   } else {
     set_error("gmresir_spmv: prec must be FP64 or FP32");

@@ -216,11 +216,46 @@ __device__ __forceinline__ T prev_inv_norm(const State& st, const T* norm_part, 
 //
 // Per tile: the SpMV products are staged in LDS and summed per row (one
 // thread per row); the row results y and (SCALED) the new basis vector
-// v_j = round(wtmp * inv_h) are staged in LDS, v_j is stored into V[:, j];
-// then wave w takes the columns c = w, w + 4, ... and each lane multiplies
-// four consecutive rows of the column (one 16-byte load) with the staged y.
-// Each lane keeps SLOTS running sums (k/4 registers instead of k), reduced
-// across the wave once at the end.  Columns c >= 4*SLOTS are left to k_dots.
+// v_j = round(wtmp / ||wtmp||) are staged in LDS, v_j is stored into V[:, j].
+// Consecutive tiles of the block are staged until TILE_ROWS rows are
+// collected (a 27-point tile has ~95 rows), then wave w takes the columns
+// c = w, w + 4, ... of those rows and each lane multiplies four consecutive
+// rows of a column (one 16-byte load) with the staged y.  Each lane keeps
+// SLOTS running sums (k/4 registers instead of k), reduced across the wave
+// once at the end.  Columns c >= 4*SLOTS are left to k_dots.
+template <typename T, typename S, int SLOTS, bool SCALED>
+__device__ __forceinline__ void project_rows(const S* __restrict__ V, long ldv, int j, int C, int base, int nrows,
+                                             const T* ys, const T* vs, T (&acc)[SLOTS], int lane, int wid) {
+  const bool aligned = (base & 3) == 0;
+  const int ngroups = (nrows + 3) >> 2;
+  for (int g = lane; g < ngroups; g += WAVE) {
+    const int rb = g * 4;
+    const bool full = aligned && rb + 4 <= nrows;
+    T yv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) yv[i] = (rb + i < nrows) ? ys[rb + i] : T(0);
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+      const int c = wid + NWAVES * q;
+      if (c < C) {
+        T vv[4];
+        if (SCALED && c == j) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) vv[i] = (rb + i < nrows) ? vs[rb + i] : T(0);
+        } else if (full) {
+          Quad<S, T>::load(V + (size_t)c * ldv + base + rb, vv);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            vv[i] = (rb + i < nrows) ? Basis<S, T>::load(V + (size_t)c * ldv + base + rb + i) : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[q] += vv[i] * yv[i];
+      }
+    }
+  }
+}
+
 template <typename T, typename S, int SLOTS, bool SCALED>
 __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict__ src, S* __restrict__ V, long ldv,
                                                      int j, T* __restrict__ w_out, State st, T* __restrict__ part,
@@ -244,11 +279,20 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict_
   const int B = gridDim.x, lb = logical_block();
   const int t0 = (int)((long)A.ntiles * lb / B);
   const int t1 = (int)((long)A.ntiles * (lb + 1) / B);
+  int base = t0 < t1 ? A.tile_row[t0] : 0;  // first row staged in ys / vs
+  int end = base;                            // one past the last staged row
   for (int t = t0; t < t1; ++t) {
     const int r0 = A.tile_row[t], r1 = A.tile_row[t + 1];
     const int p0 = A.rowptr[r0], p1 = A.rowptr[r1];
     const int len = p1 - p0;
     const int nrows = r1 - r0;
+    if (r1 - base > TILE_ROWS) {
+      // the staged rows are full: project them, then start a new batch
+      project_rows<T, S, SLOTS, SCALED>(V, ldv, j, C, base, end - base, ys, vs, acc, lane, wid);
+      __syncthreads();
+      base = r0;
+    }
+    const int off = r0 - base;
     if (len <= TILE_NNZ) {
       if (SCALED) stage_products<T>(A, p0, len, xs, prod);
       else stage_products<T>(A, p0, len, XPlain<T>{src}, prod);
@@ -259,11 +303,11 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict_
         T y = T(0);
         for (int q = q0; q < q1; ++q) y += prod[q];
         w_out[r] = y;
-        ys[rr] = y;
+        ys[off + rr] = y;
         if (SCALED) {
           const T vj = xs(r);
           Basis<S, T>::store(V + (size_t)j * ldv + r, vj);
-          vs[rr] = vj;
+          vs[off + rr] = vj;
         }
       }
     } else {
@@ -273,46 +317,18 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict_
       y = block_sum(y, s_red);
       if (threadIdx.x == 0) {
         w_out[r0] = y;
-        ys[0] = y;
+        ys[off] = y;
         if (SCALED) {
           const T vj = xs(r0);
           Basis<S, T>::store(V + (size_t)j * ldv + r0, vj);
-          vs[0] = vj;
+          vs[off] = vj;
         }
       }
     }
-    __syncthreads();
-    // projection of the tile's rows on the columns of this wave
-    const bool aligned = (r0 & 3) == 0;
-    const int ngroups = (nrows + 3) >> 2;
-    for (int g = lane; g < ngroups; g += WAVE) {
-      const int rb = g * 4;
-      const bool full = aligned && rb + 4 <= nrows;
-      T yv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) yv[i] = (rb + i < nrows) ? ys[rb + i] : T(0);
-#pragma unroll
-      for (int q = 0; q < SLOTS; ++q) {
-        const int c = wid + NWAVES * q;
-        if (c < C) {
-          T vv[4];
-          if (SCALED && c == j) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) vv[i] = (rb + i < nrows) ? vs[rb + i] : T(0);
-          } else if (full) {
-            Quad<S, T>::load(V + (size_t)c * ldv + r0 + rb, vv);
-          } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              vv[i] = (rb + i < nrows) ? Basis<S, T>::load(V + (size_t)c * ldv + r0 + rb + i) : T(0);
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) acc[q] += vv[i] * yv[i];
-        }
-      }
-    }
-    __syncthreads();
+    end = r1;
+    __syncthreads();  // y staged; prod free for the next tile
   }
+  if (end > base) project_rows<T, S, SLOTS, SCALED>(V, ldv, j, C, base, end - base, ys, vs, acc, lane, wid);
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q) {
     const int c = wid + NWAVES * q;
