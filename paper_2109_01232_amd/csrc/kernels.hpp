@@ -396,34 +396,35 @@ __device__ __forceinline__ void store_rows(T* p, const T (&v)[R]) {
   else p[0] = v[0];
 }
 
-// The block's four waves share rows and split the columns: wave w holds
-// columns c = w + 4q (q < SLOTS) of R rows per lane in registers.  Per step of
-// 64 R rows: each wave forms its part of (V h1)[r] over its columns, the four
-// parts meet in LDS and are added in a fixed order, every wave computes
-// w' = w - V h1 for the step's rows, and then accumulates V[r, c] w'[r] for
-// its own columns from the registers.  So each V element is loaded once and
-// each lane keeps only SLOTS accumulators.  Workspace vectors and basis
-// columns are padded to ldv rows, so whole R-row loads stay in bounds; the
-// padded rows are masked to zero.
-template <typename T, typename S, int SLOTS, int R>
-__global__ __launch_bounds__(BLOCK) void k_update_proj(int n, const T* __restrict__ w_in, T* __restrict__ w_out,
-                                                       const S* __restrict__ V, long ldv, int k, State st,
-                                                       T* __restrict__ part) {
+// The block's WV waves (4 or 8) share rows and split the columns: wave w
+// holds columns c = w + WV q (q < SLOTS) of R rows per lane in registers.
+// Per step of 64 R rows: each wave forms its part of (V h1)[r] over its
+// columns, the parts meet in LDS and are added in a fixed order, every wave
+// computes w' = w - V h1 for the step's rows, and then accumulates
+// V[r, c] w'[r] for its own columns from the registers.  So each V element is
+// loaded once and each lane keeps only SLOTS accumulators.  (Eight waves for
+// the widest bases keep SLOTS, and so the registers per lane, at 16.)
+// Workspace vectors and basis columns are padded to ldv rows, so whole R-row
+// loads stay in bounds; the padded rows are masked to zero.
+template <typename T, typename S, int SLOTS, int R, int WV>
+__global__ __launch_bounds__(WV * WAVE) void k_update_proj(int n, const T* __restrict__ w_in, T* __restrict__ w_out,
+                                                           const S* __restrict__ V, long ldv, int k, State st,
+                                                           T* __restrict__ part) {
   if (st.hdr->flags & F_DONE) return;
-  constexpr int KMAX = NWAVES * SLOTS;
+  constexpr int KMAX = WV * SLOTS;
   constexpr int STEP = WAVE * R;
   __shared__ T s_h[KMAX];
-  __shared__ T s_part[2][NWAVES][STEP];
+  __shared__ T s_part[2][WV][STEP];
   __shared__ T s_vals[KMAX];
   const double* h1 = st.h1_of(k - 1);
-  for (int c = threadIdx.x; c < KMAX; c += BLOCK) s_h[c] = c < k ? (T)h1[c] : T(0);
+  for (int c = threadIdx.x; c < KMAX; c += WV * WAVE) s_h[c] = c < k ? (T)h1[c] : T(0);
   __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);  // wave-uniform: hq in scalar registers
   T hq[SLOTS], acc[SLOTS];
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q) {
-    hq[q] = s_h[wid + NWAVES * q];
+    hq[q] = s_h[wid + WV * q];
     acc[q] = T(0);
   }
   int r0, r1;
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(BLOCK) void k_update_proj(int n, const T* __restric
     for (int i = 0; i < R; ++i) s[i] = T(0);
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) {
-      const int c = wid + NWAVES * q;
+      const int c = wid + WV * q;
       if (c < k && nv > 0) {
         Rows<S, T, R>::load(V + (size_t)c * ldv + r, vr[q]);
 #pragma unroll
@@ -464,7 +465,8 @@ __global__ __launch_bounds__(BLOCK) void k_update_proj(int n, const T* __restric
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int e = R * lane + i;
-      const T t = (s_part[buf][0][e] + s_part[buf][1][e]) + (s_part[buf][2][e] + s_part[buf][3][e]);
+      T t = (s_part[buf][0][e] + s_part[buf][1][e]) + (s_part[buf][2][e] + s_part[buf][3][e]);
+      if constexpr (WV == 8) t += (s_part[buf][4][e] + s_part[buf][5][e]) + (s_part[buf][6][e] + s_part[buf][7][e]);
       wv[i] = (i < nv) ? wv[i] - t : T(0);
     }
     if (wid == 0 && nv > 0) {
@@ -481,14 +483,14 @@ __global__ __launch_bounds__(BLOCK) void k_update_proj(int n, const T* __restric
   }
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q) {
-    const int c = wid + NWAVES * q;
+    const int c = wid + WV * q;
     if (c < k) {
       const T v = wave_sum(acc[q]);
       if (lane == 0) s_vals[c] = v;
     }
   }
   __syncthreads();
-  store_partials(s_vals, k, part);
+  for (int c = threadIdx.x; c < k; c += WV * WAVE) part[(size_t)c * MAX_BLOCKS + blockIdx.x] = s_vals[c];
 }
 
 // w_out = w_in - V h (any k <= MAX_RESTART+1); h from h_src.
