@@ -217,8 +217,9 @@ __device__ __forceinline__ T prev_inv_norm(const State& st, const T* norm_part, 
 // Per tile: the SpMV products are staged in LDS and summed per row (one
 // thread per row); the row results y and (SCALED) the new basis vector
 // v_j = round(wtmp / ||wtmp||) are staged in LDS, v_j is stored into V[:, j].
-// Consecutive tiles of the block are staged until TILE_ROWS rows are
-// collected (a 27-point tile has ~95 rows), then wave w takes the columns
+// Consecutive tiles of the block are staged until up to 1024 rows (fp32;
+// 512 for fp64) are collected (a 27-point tile has ~95 rows, a 7-point one
+// ~365), then wave w takes the columns
 // c = w, w + 4, ... of those rows and each lane multiplies four consecutive
 // rows of a column (one 16-byte load) with the staged y.  Each lane keeps
 // SLOTS running sums (k/4 registers instead of k), reduced across the wave
@@ -262,9 +263,13 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict_
                                                      const T* __restrict__ norm_part, int nB) {
   if (st.hdr->flags & F_DONE) return;
   constexpr int KMAX = NWAVES * SLOTS;
+  // rows staged for one projection pass: several short tiles at once, so
+  // the 64 lanes of a wave get whole groups of 4 rows (fp64 keeps 512 rows
+  // to leave LDS for occupancy)
+  constexpr int STAGE_ROWS = sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS;
   T* prod = dyn_lds<T>();  // one entry per nonzero of the largest tile
-  __shared__ T ys[TILE_ROWS];
-  __shared__ T vs[TILE_ROWS];
+  __shared__ T ys[STAGE_ROWS];
+  __shared__ T vs[STAGE_ROWS];
   __shared__ T s_vals[KMAX];
   __shared__ T s_red[NWAVES];
   const T* vals = (const T*)A.vals;
@@ -286,7 +291,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict_
     const int p0 = A.rowptr[r0], p1 = A.rowptr[r1];
     const int len = p1 - p0;
     const int nrows = r1 - r0;
-    if (r1 - base > TILE_ROWS) {
+    if (r1 - base > STAGE_ROWS) {
       // the staged rows are full: project them, then start a new batch
       project_rows<T, S, SLOTS, SCALED>(V, ldv, j, C, base, end - base, ys, vs, acc, lane, wid);
       __syncthreads();
