@@ -527,8 +527,8 @@ struct Ctx {
   }
 
   void update_proj_dispatch(int k) {
-    // fp64 values take two registers: half the rows per lane
-    constexpr int R = sizeof(T) == 8 ? 2 : 4;
+    // 16-byte basis loads: 2 fp64, 4 fp32 or 8 bf16 rows per lane
+    constexpr int R = 16 / sizeof(S);
     if (k <= 16) launch_update_proj<4, R, 4>(k);
     else if (k <= 32) launch_update_proj<8, R, 4>(k);
     else if (k <= 48) launch_update_proj<12, R, 4>(k);
@@ -932,8 +932,8 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
     while (r < n && r - r0 < TILE_ROWS && (int64_t)rp[r + 1] - rp[r0] <= TILE_NNZ) ++r;
     if (r == r0) {
       r = r0 + 1;  // one row longer than a tile
-    } else if (r < n && (r & 3) && (r & ~(int64_t)3) > r0) {
-      r &= ~(int64_t)3;  // end tiles on a multiple of 4 rows (16-byte basis loads)
+    } else if (r < n && (r & 7) && (r & ~(int64_t)7) > r0) {
+      r &= ~(int64_t)7;  // end tiles on a multiple of 8 rows (16-byte loads of 4 fp32 / 8 bf16 basis rows)
     }
     tiles.push_back((int32_t)r);
     r0 = r;

@@ -200,6 +200,48 @@ struct QuadStore<double> {
   }
 };
 
+// R consecutive rows of one basis column as one vector load, kept packed in
+// registers (bf16: 8 rows in 16 bytes) and unpacked to T on use.
+template <typename S, typename T, int R>
+struct Packed;
+template <>
+struct Packed<float, float, 4> {
+  using type = float4;
+  static __device__ __forceinline__ type load(const float* p) { return *(const float4*)p; }
+  static __device__ __forceinline__ type zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  static __device__ __forceinline__ float get(const type& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+  static __device__ __forceinline__ void hold(type&) {}
+};
+template <>
+struct Packed<double, double, 2> {
+  using type = double2;
+  static __device__ __forceinline__ type load(const double* p) { return *(const double2*)p; }
+  static __device__ __forceinline__ type zero() { return make_double2(0.0, 0.0); }
+  static __device__ __forceinline__ double get(const type& v, int i) { return i == 0 ? v.x : v.y; }
+  static __device__ __forceinline__ void hold(type&) {}
+};
+template <>
+struct Packed<double, double, 1> {
+  using type = double;
+  static __device__ __forceinline__ type load(const double* p) { return *p; }
+  static __device__ __forceinline__ type zero() { return 0.0; }
+  static __device__ __forceinline__ double get(const type& v, int) { return v; }
+  static __device__ __forceinline__ void hold(type&) {}
+};
+template <>
+struct Packed<bf16_t, float, 8> {
+  using type = uint4;
+  static __device__ __forceinline__ type load(const bf16_t* p) { return *(const uint4*)p; }
+  static __device__ __forceinline__ type zero() { return make_uint4(0u, 0u, 0u, 0u); }
+  static __device__ __forceinline__ float get(const type& v, int i) {
+    const uint32_t w = (i >> 1) == 0 ? v.x : (i >> 1) == 1 ? v.y : (i >> 1) == 2 ? v.z : v.w;
+    return __uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
+  }
+  // keeps the 8 rows packed between their two uses (otherwise the compiler
+  // holds all 8 unpacked values, twice the registers)
+  static __device__ __forceinline__ void hold(type& v) { asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w)); }
+};
+
 // 1 / ||w''|| of the previous iteration, the scale of the next basis vector:
 // summed from the partials k_update_norm left (nB > 0) in the order the
 // Givens step sums them (so both get the same bits), or read from the state
@@ -220,38 +262,62 @@ __device__ __forceinline__ T prev_inv_norm(const State& st, const T* norm_part, 
 // Consecutive tiles of the block are staged until up to 1024 rows (fp32;
 // 512 for fp64) are collected (a 27-point tile has ~95 rows, a 7-point one
 // ~365), then wave w takes the columns
-// c = w, w + 4, ... of those rows and each lane multiplies four consecutive
-// rows of a column (one 16-byte load) with the staged y.  Each lane keeps
+// c = w, w + 4, ... of those rows and each lane multiplies a group of
+// consecutive rows of a column (one 16-byte load: 4 fp32 or 8 bf16 rows) with
+// the staged y.  Each lane keeps
 // SLOTS running sums (k/4 registers instead of k), reduced across the wave
 // once at the end.  Columns c >= 4*SLOTS are left to k_dots.
+template <typename S, typename T>
+struct ProjGroup;  // rows per lane of the projection: one 16-byte load (fp64: two)
+template <>
+struct ProjGroup<float, float> {
+  static constexpr int G = 4;
+  static __device__ __forceinline__ void load(const float* p, float (&v)[4]) { Quad<float, float>::load(p, v); }
+};
+template <>
+struct ProjGroup<double, double> {
+  static constexpr int G = 4;
+  static __device__ __forceinline__ void load(const double* p, double (&v)[4]) { Quad<double, double>::load(p, v); }
+};
+template <>
+struct ProjGroup<bf16_t, float> {
+  static constexpr int G = 8;
+  static __device__ __forceinline__ void load(const bf16_t* p, float (&v)[8]) {
+    const uint4 q = *(const uint4*)p;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = Packed<bf16_t, float, 8>::get(q, i);
+  }
+};
+
 template <typename T, typename S, int SLOTS, bool SCALED>
 __device__ __forceinline__ void project_rows(const S* __restrict__ V, long ldv, int j, int C, int base, int nrows,
                                              const T* ys, const T* vs, T (&acc)[SLOTS], int lane, int wid) {
-  const bool aligned = (base & 3) == 0;
-  const int ngroups = (nrows + 3) >> 2;
+  constexpr int G = ProjGroup<S, T>::G;
+  const bool aligned = (base % G) == 0;
+  const int ngroups = (nrows + G - 1) / G;
   for (int g = lane; g < ngroups; g += WAVE) {
-    const int rb = g * 4;
-    const bool full = aligned && rb + 4 <= nrows;
-    T yv[4];
+    const int rb = g * G;
+    const bool full = aligned && rb + G <= nrows;
+    T yv[G];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) yv[i] = (rb + i < nrows) ? ys[rb + i] : T(0);
+    for (int i = 0; i < G; ++i) yv[i] = (rb + i < nrows) ? ys[rb + i] : T(0);
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) {
       const int c = wid + NWAVES * q;
       if (c < C) {
-        T vv[4];
+        T vv[G];
         if (SCALED && c == j) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) vv[i] = (rb + i < nrows) ? vs[rb + i] : T(0);
+          for (int i = 0; i < G; ++i) vv[i] = (rb + i < nrows) ? vs[rb + i] : T(0);
         } else if (full) {
-          Quad<S, T>::load(V + (size_t)c * ldv + base + rb, vv);
+          ProjGroup<S, T>::load(V + (size_t)c * ldv + base + rb, vv);
         } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < G; ++i)
             vv[i] = (rb + i < nrows) ? Basis<S, T>::load(V + (size_t)c * ldv + base + rb + i) : T(0);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[q] += vv[i] * yv[i];
+        for (int i = 0; i < G; ++i) acc[q] += vv[i] * yv[i];
       }
     }
   }
@@ -401,6 +467,27 @@ __device__ __forceinline__ void store_rows(T* p, const T (&v)[R]) {
   else p[0] = v[0];
 }
 
+// R consecutive rows of a work vector (T) with 16-byte accesses.
+template <typename T, int R>
+__device__ __forceinline__ void load_vec(const T* p, T (&v)[R]) {
+  if constexpr (R == 8) {
+    const float4 a = *(const float4*)p, b = *(const float4*)(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    Rows<T, T, R>::load(p, v);
+  }
+}
+template <typename T, int R>
+__device__ __forceinline__ void store_vec(T* p, const T (&v)[R]) {
+  if constexpr (R == 8) {
+    *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
+    *(float4*)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+  } else {
+    store_rows<T, R>(p, v);
+  }
+}
+
 // The block's WV waves (4 or 8) share rows and split the columns: wave w
 // holds columns c = w + WV q (q < SLOTS) of R rows per lane in registers.
 // Per step of 64 R rows: each wave forms its part of (V h1)[r] over its
@@ -438,31 +525,26 @@ __global__ __launch_bounds__(WV * WAVE) void k_update_proj(int n, const T* __res
   for (int base = r0; base < r1; base += STEP, buf ^= 1) {
     const int r = base + R * lane;
     const int nv = r1 - r;  // rows of this lane inside the block's range (may be <= 0 or > R)
-    T vr[SLOTS][R];
+    using P = Packed<S, T, R>;
+    typename P::type vr[SLOTS];
     T s[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) s[i] = T(0);
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) {
       const int c = wid + WV * q;
-      if (c < k && nv > 0) {
-        Rows<S, T, R>::load(V + (size_t)c * ldv + r, vr[q]);
+      vr[q] = (c < k && nv > 0) ? P::load(V + (size_t)c * ldv + r) : P::zero();
 #pragma unroll
-        for (int i = 0; i < R; ++i)
-          if (i >= nv) vr[q][i] = T(0);
-      } else {
-#pragma unroll
-        for (int i = 0; i < R; ++i) vr[q][i] = T(0);
-      }
-#pragma unroll
-      for (int i = 0; i < R; ++i) s[i] += hq[q] * vr[q][i];
+      for (int i = 0; i < R; ++i) s[i] += hq[q] * ((i < nv) ? P::get(vr[q], i) : T(0));
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) s_part[buf][wid][R * lane + i] = s[i];
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) P::hold(vr[q]);
     T wv[R];
     if (nv > 0) {
-      Rows<T, T, R>::load(w_in + r, wv);
+      load_vec<T, R>(w_in + r, wv);
     } else {
 #pragma unroll
       for (int i = 0; i < R; ++i) wv[i] = T(0);
@@ -476,7 +558,7 @@ __global__ __launch_bounds__(WV * WAVE) void k_update_proj(int n, const T* __res
     }
     if (wid == 0 && nv > 0) {
       if (nv >= R) {
-        store_rows<T, R>(w_out + r, wv);
+        store_vec<T, R>(w_out + r, wv);
       } else {
         for (int i = 0; i < nv; ++i) w_out[r + i] = wv[i];
       }
@@ -484,7 +566,7 @@ __global__ __launch_bounds__(WV * WAVE) void k_update_proj(int n, const T* __res
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q)
 #pragma unroll
-      for (int i = 0; i < R; ++i) acc[q] += vr[q][i] * wv[i];
+      for (int i = 0; i < R; ++i) acc[q] += ((i < nv) ? P::get(vr[q], i) : T(0)) * wv[i];
   }
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q) {
