@@ -219,7 +219,6 @@ __device__ __forceinline__ T block_sum(T v, T* lds /* NWAVES */) {
 // of the XCD every time.)
 constexpr int MAX_BLOCKS = 1024;
 constexpr int RED_BATCH = 4;                   // columns reduced per wave and batch
-constexpr int RED_LOADS = MAX_BLOCKS / WAVE;   // partials per lane and column
 constexpr int PART_COLS = 136;                 // partial columns in the workspace (>= 129 + 1)
 constexpr int NORM_SLOT = PART_COLS - 1;       // column of the ||w''||^2 partials of k_update_norm
 
@@ -228,54 +227,41 @@ __device__ __forceinline__ void store_partials(const T* vals, int nv, T* part) {
   for (int c = threadIdx.x; c < nv; c += BLOCK) part[(size_t)c * MAX_BLOCKS + blockIdx.x] = vals[c];
 }
 
-// Sum of one column of partials by one wave: lane l adds b = l + 64 i in
-// order of i, then the lanes by a fixed butterfly (the order reduce_partials
-// uses, so both give the same bits).  Every lane returns the sum.
-template <typename T>
-__device__ __forceinline__ T wave_reduce_column(const T* col, int B) {
+// Lane l's share of one column of B partials: b = l + 64 i in order of i,
+// NL loads all issued before the adds (branch-free: out-of-range blocks read
+// a valid address and add 0).
+template <int NL, typename T>
+__device__ __forceinline__ T lane_share(const T* col, int B) {
   const int lane = threadIdx.x & (WAVE - 1);
   T s = T(0);
 #pragma unroll
-  for (int i = 0; i < RED_LOADS; ++i) {
+  for (int i = 0; i < NL; ++i) {
     const int b = lane + WAVE * i;
     const int bc = b < B ? b : B - 1;
     const T v = col[bc];
     s += (b < B) ? v : T(0);
   }
+  return s;
+}
+
+// Sum of one column of partials by one wave: lane shares in order, then the
+// lanes by a fixed butterfly (the order reduce_partials uses, so both give
+// the same bits).  Every lane returns the sum.
+template <typename T>
+__device__ __forceinline__ T wave_reduce_column(const T* col, int B) {
+  const T s = B <= MAX_BLOCKS / 2 ? lane_share<MAX_BLOCKS / 2 / WAVE>(col, B) : lane_share<MAX_BLOCKS / WAVE>(col, B);
   return wave_sum(s);
 }
 
-// out[c] = sum over the B producer blocks of part[c][b], one wave per column:
-// lane l sums b = l + 64 i in order of i, then the lanes by a fixed butterfly.
-// All loads of a batch are issued before any add.  With extra != nullptr the
-// last wave first sums one more column, out[nv] = sum of extra[b], b < nE, in
-// the same order (bitwise the result of a separate call with nv = 1).  out is
-// LDS; ends with a barrier.
-template <typename T>
-__device__ __forceinline__ void reduce_partials(const T* part, int nv, int B, T* out, const T* extra = nullptr,
-                                                int nE = 0) {
+template <int NL, typename T>
+__device__ __forceinline__ void reduce_batches(const T* part, int nv, int B, T* out, int wid, int nwaves) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  const int nwaves = blockDim.x / WAVE;
-  if (extra && wid == nwaves - 1) {
-    T s = T(0);
-#pragma unroll
-    for (int i = 0; i < RED_LOADS; ++i) {
-      const int b = lane + WAVE * i;
-      const int bc = b < nE ? b : nE - 1;
-      const T v = extra[bc];
-      s += (b < nE) ? v : T(0);
-    }
-    const T t = wave_sum(s);
-    if (lane == 0) out[nv] = t;
-  }
   for (int c0 = wid * RED_BATCH; c0 < nv; c0 += nwaves * RED_BATCH) {
     T s[RED_BATCH];
 #pragma unroll
     for (int q = 0; q < RED_BATCH; ++q) s[q] = T(0);
-    // branch-free: out-of-range blocks read a valid address and add 0
 #pragma unroll
-    for (int i = 0; i < RED_LOADS; ++i) {
+    for (int i = 0; i < NL; ++i) {
       const int b = lane + WAVE * i;
       const int bc = b < B ? b : B - 1;
 #pragma unroll
@@ -291,6 +277,24 @@ __device__ __forceinline__ void reduce_partials(const T* part, int nv, int B, T*
       if (lane == 0 && c0 + q < nv) out[c0 + q] = t;
     }
   }
+}
+
+// out[c] = sum over the B producer blocks of part[c][b], one wave per column
+// (batches of RED_BATCH columns), each as wave_reduce_column.  With
+// extra != nullptr the last wave first sums one more column, out[nv] = sum of
+// extra[b], b < nE, the same way.  out is LDS; ends with a barrier.
+template <typename T>
+__device__ __forceinline__ void reduce_partials(const T* part, int nv, int B, T* out, const T* extra = nullptr,
+                                                int nE = 0) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int nwaves = blockDim.x / WAVE;
+  if (extra && wid == nwaves - 1) {
+    const T t = wave_reduce_column(extra, nE);
+    if (lane == 0) out[nv] = t;
+  }
+  if (B <= MAX_BLOCKS / 2) reduce_batches<MAX_BLOCKS / 2 / WAVE>(part, nv, B, out, wid, nwaves);
+  else reduce_batches<MAX_BLOCKS / WAVE>(part, nv, B, out, wid, nwaves);
   __syncthreads();
 }
 

@@ -69,7 +69,8 @@ int device_cus(int dev) {
   return cus;
 }
 
-int resident_grid(const void* kern, size_t smem, int threads = BLOCK) {
+// blocks of kern resident on the whole device at once (before any cap)
+int resident_blocks(const void* kern, size_t smem, int threads) {
   static std::mutex mu;
   static std::map<std::tuple<int, const void*, size_t>, int> cache;
   int dev = 0;
@@ -81,10 +82,14 @@ int resident_grid(const void* kern, size_t smem, int threads = BLOCK) {
   }
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, smem) != hipSuccess || nb <= 0) nb = 1;
-  int g = std::min(MAX_GRID, device_cus(dev) * nb);
+  const int g = device_cus(dev) * nb;
   std::lock_guard<std::mutex> lk(mu);
   cache[{dev, kern, smem}] = g;
   return g;
+}
+
+int resident_grid(const void* kern, size_t smem, int threads = BLOCK) {
+  return std::min(MAX_GRID, resident_blocks(kern, smem, threads));
 }
 
 int grid_rows(const void* kern, int64_t n, int threads = BLOCK) {
@@ -98,7 +103,8 @@ int grid_rows(const void* kern, int64_t n, int threads = BLOCK) {
 // vs 3.7 TB/s on the 7-point 150^3 polynomial steps).  Kernels that leave
 // per-block partial sums run one resident wave of blocks (at most MAX_GRID),
 // each over a contiguous range of tiles, which amortises their prologue and
-// partial sums (one tile per block measured 17 % slower there).
+// partial sums (measured: one tile per block 17 % slower on the 5-point
+// 1000^2 system, 2048 blocks 10 % slower on the 27-point 128^3 system).
 int grid_tiles(int ntiles) { return std::max(1, ntiles); }
 int grid_tiles_part(const void* kern, int ntiles, size_t smem) {
   return std::max(1, std::min(resident_grid(kern, smem), ntiles));
