@@ -17,6 +17,7 @@
 #include <map>
 #include <tuple>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "gmresir.h"
@@ -39,6 +40,7 @@ struct gmresir_matrix {
 namespace {
 
 constexpr int MAX_GRID = 1024;  // <= MAX_BLOCKS (partials per reduction)
+constexpr int64_t GRAPH_MAX_N = 1 << 18;  // cycles of smaller systems run as HIP graphs
 constexpr size_t ALIGN = 256;
 
 #define HIP_TRY(expr)                                                              \
@@ -253,12 +255,45 @@ struct Prof {
     }
     return pool[used++];
   }
+  // Graph recording (rec != nullptr): launches become kernel nodes chained
+  // after `last`, and their bookings are kept in `recorded`.
+  hipGraph_t rec = nullptr;
+  hipGraphNode_t last = nullptr;
+  bool rec_failed = false;
+  std::vector<Entry> recorded;
+
+  template <typename Tup, size_t... I>
+  static void arg_ptrs(Tup& t, void** p, std::index_sequence<I...>) {
+    ((p[I] = (void*)&std::get<I>(t)), ...);
+  }
+
   // Launch kern on strm and book it under category cat with b algorithmic
   // bytes; when profiling, the kernel's own start and end are recorded
   // (hipExtLaunchKernel events, no extra packets between kernels).
-  template <typename K, typename... Args>
-  void launch(int cat, double b, K kern, dim3 grid, dim3 block, size_t smem, hipStream_t strm, Args... args) {
+  template <typename... P, typename... Args>
+  void launch(int cat, double b, void (*kern)(P...), dim3 grid, dim3 block, size_t smem, hipStream_t strm,
+              Args... args) {
     Entry e{cat, b, tag, early, nullptr, nullptr};
+    if (rec) {
+      // node arguments converted to the kernel's own parameter types
+      std::tuple<std::remove_cv_t<std::remove_reference_t<P>>...> t(args...);
+      void* ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1];
+      arg_ptrs(t, ptrs, std::index_sequence_for<P...>{});
+      hipKernelNodeParams kp{};
+      kp.func = (void*)kern;
+      kp.gridDim = grid;
+      kp.blockDim = block;
+      kp.sharedMemBytes = (unsigned)smem;
+      kp.kernelParams = ptrs;
+      kp.extra = nullptr;
+      hipGraphNode_t node = nullptr;
+      if (hipGraphAddKernelNode(&node, rec, last ? &last : nullptr, last ? 1 : 0, &kp) != hipSuccess)
+        rec_failed = true;
+      else
+        last = node;
+      recorded.push_back(e);
+      return;
+    }
     if (!on) {
       hipLaunchKernelGGL(kern, grid, block, smem, strm, args...);
     } else {
@@ -587,6 +622,58 @@ struct Ctx {
     update_norm(j);
   }
 
+  // Small systems are bound by the host's launch rate (~5 kernels of a few
+  // microseconds per step): their cycles run as one HIP graph, recorded on
+  // first use and replayed for every later cycle of the same length (all
+  // kernel arguments are fixed per position in the cycle; the per-cycle state
+  // lives in the workspace).
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_kmax = -1;
+  bool graph_ok = false;
+  std::vector<typename Prof::Entry> graph_entries;
+
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+    graph_kmax = -1;
+  }
+  ~Ctx() { drop_graph(); }
+
+  void run_cycle(int kmax) {
+    if (!graph_ok) {
+      cycle(kmax);
+      return;
+    }
+    if (graph_kmax != kmax) {
+      drop_graph();
+      bool ok = hipGraphCreate(&graph, 0) == hipSuccess;
+      if (ok) {
+        prof->rec = graph;
+        prof->last = nullptr;
+        prof->rec_failed = false;
+        prof->recorded.clear();
+        cycle(kmax);
+        prof->rec = nullptr;
+        ok = !prof->rec_failed && hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      }
+      if (!ok) {
+        // fall back to direct launches for the rest of the solve
+        (void)hipGetLastError();
+        drop_graph();
+        graph_ok = false;
+        cycle(kmax);
+        return;
+      }
+      graph_kmax = kmax;
+      graph_entries = prof->recorded;
+    }
+    (void)hipGraphLaunch(graph_exec, stream);
+    prof->pend.insert(prof->pend.end(), graph_entries.begin(), graph_entries.end());
+  }
+
   // the Arnoldi steps of one cycle, ending with its last Givens step
   void cycle(int kmax) {
     for (int j = 0; j < kmax; ++j) iteration(j, kmax);
@@ -690,6 +777,7 @@ int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresi
   prof.on = p->profile == 1;
   prof.stream = stream;
   Ctx<T, S> c(A, ws, L, stream, &prof);
+  c.graph_ok = !prof.on && A->n <= GRAPH_MAX_N;
   if (L.poly) {
     const char* why = "";
     if (!build_poly_program(p->poly_degree + 1, roots, c.prog, &why)) {
@@ -745,7 +833,7 @@ int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresi
     int first = 1;
     while (used < budget) {
       const int kmax = (int)std::min<int64_t>(m, budget - used);
-      c.cycle(kmax);
+      c.run_cycle(kmax);
       c.backsolve(kmax);
       if (single && !L.poly) {
         c.correct_x(x, kmax);

@@ -208,6 +208,26 @@ def test_deterministic(cfg1):
     assert torch.equal(xa, xb) and da["iters"] == db["iters"]
 
 
+def test_graph_replay_matches_direct_launches(cfg1):
+    """Systems up to 2^18 rows run their cycles as a recorded HIP graph,
+    replayed once per refinement with eager kernels (residual, cast, host
+    read) in between; profiling switches to direct launches.  Both give the
+    same bits on every refinement (fp32 inner, fp64 inner, bf16 basis, a
+    multi-cycle inner cap, and two solves in a row)."""
+    s, M = cfg1
+    b = dev_tensor(s.b)
+    for kw in (dict(restart=50, inner="fp32"), dict(restart=30, inner="fp64"),
+               dict(restart=40, inner="fp32", basis="bf16"), dict(restart=20, inner="fp32", inner_cap=60)):
+        say("graph vs direct", kw)
+        xg, dg, hg = B.solve(M, b, rtol=1e-10, hist_cap=20000, **kw)
+        xg2, dg2, _ = B.solve(M, b, rtol=1e-10, **kw)
+        xd, dd, hd = B.solve(M, b, rtol=1e-10, hist_cap=20000, profile=1, **kw)
+        assert dg["refinements"] >= 3
+        assert torch.equal(xg, xd) and torch.equal(xg, xg2)
+        assert dg["iters"] == dd["iters"] and dg["refinements"] == dd["refinements"]
+        assert np.array_equal(hg, hd)
+
+
 def test_resume_equals_single_call(cfg1):
     s, M = cfg1
     say("resume")
