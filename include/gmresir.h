@@ -113,7 +113,7 @@ size_t gmresir_matrix_storage_bytes(int64_t n, int64_t nnz);
    must stay alive and unchanged while the handle is used).  storage: device
    buffer of gmresir_matrix_storage_bytes(n, nnz) bytes, 256-byte aligned,
    owned by the caller and written here.  The row pointers are copied to the
-   host once to cut the rows into tiles of at most 512 rows / 6144 nonzeros.
+   host once to cut the rows into tiles of at most 512 rows / 2560 nonzeros.
    Errors: INVALID_ARG (null pointer, n < 1, nnz < 0, nnz >= 2^31, rowptr not
    monotone or rowptr[n] != nnz), WORKSPACE (storage too small), HIP. */
 int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,

@@ -213,8 +213,8 @@ __device__ __forceinline__ T block_sum(T v, T* lds /* NWAVES */) {
 
 // Cross-block reductions are two kernels: the producer grid stores one
 // partial vector per block (column-major, part[c * MAX_BLOCKS + block]) and a
-// one-block tail kernel sums them in a fixed order after the kernel boundary
-// has published them.  (A "last block" ticket inside the producer would need
+// tail kernel sums them in a fixed order after the kernel boundary has
+// published them.  (A "last block" ticket inside the producer would need
 // a device-scope release per block, which on gfx950 writes back the whole L2
 // of the XCD every time.)
 constexpr int MAX_BLOCKS = 1024;

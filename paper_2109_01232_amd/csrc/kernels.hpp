@@ -601,11 +601,12 @@ __global__ __launch_bounds__(BLOCK) void k_update(int n, const T* __restrict__ w
 }
 
 // ---------------------------------------------------------------------------
-// third kernel: second-pass update + norm + Hessenberg column + Givens
+// third kernel: second-pass update + norm; the Givens step
 // ---------------------------------------------------------------------------
 
-// Executed by the last block of k_update_norm.  Mirrors the least-squares
-// update of Algorithm 1 done incrementally with Givens rotations.  The
+// The least-squares update of Algorithm 1 done incrementally with Givens
+// rotations, by one block of any size (the extra block of
+// k_reduce_h1_givens, or k_norm_givens after a cycle's last step).  The
 // column and the earlier rotations are staged in LDS so the sequential part
 // (thread 0) touches no global memory.
 template <typename T>
@@ -838,7 +839,7 @@ __global__ __launch_bounds__(BLOCK) void k_backsolve(State st) {
 // outer (fp64) refinement kernels
 // ---------------------------------------------------------------------------
 
-// Zero the state header (tickets, flags) without hipMemsetAsync.
+// Reset the state header without hipMemsetAsync (safe inside captured graphs).
 __global__ void k_init_state(State st, double rtol, int check_mode, double gamma0) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     StateHdr* hd = st.hdr;
