@@ -278,6 +278,33 @@ def test_restart_lengths_and_fallbacks(m):
         assert np.max(np.abs(h[:k] - np.array(ref.hist[:k]))) <= tol
 
 
+@pytest.mark.parametrize("m", [20, 70, 100, 130])
+@pytest.mark.parametrize("inner,basis", [("fp64", "fp64"), ("fp32", "fp32"), ("fp32", "bf16")])
+def test_ragged_rows_every_basis_width(m, inner, basis):
+    """n = 37^2 = 1369 (not a multiple of the 4- and 8-row groups of the
+    vector loads, so the padded rows must be masked), every column-count
+    class of the fused kernels (4/8 waves, packed 8-row bf16 loads) and the
+    fallbacks past 128 columns: the first cycle against the oracle's."""
+    A = P.conv_diff(2, 37, 40.0, (1.0, -0.5))
+    u = np.random.default_rng(m).uniform(-1, 1, A.n)
+    bb = A.scipy() @ u
+    M = B.Matrix.from_csr(A)
+    b = dev_tensor(bb)
+    say("ragged", m, inner, basis)
+    x, d, h = B.solve(M, b, restart=m, inner=inner, basis=basis, rtol=1e-10, check_mode=0, max_iters=20000,
+                      hist_cap=20000)
+    if inner == "fp64":
+        ref = L.gmres(A, bb, m=m, rtol=1e-10, check_mode=0, max_iters=m)
+        tol = 1e-10
+    else:
+        ref = L.gmres_ir(A, bb, m=m, rtol=1e-10, inner="fp32", basis=basis, check_mode=0, max_iters=m)
+        tol = HIST_TOL_FP32 if basis == "fp32" else HIST_TOL_BF16
+    k = min(m, len(ref.hist))
+    assert np.max(np.abs(h[:k] - np.array(ref.hist[:k]))) <= tol
+    assert d["status"] == B.OK and d["rel_resid_true"] <= 1e-10
+    assert np.linalg.norm(bb - A.scipy() @ x.cpu().numpy()) / np.linalg.norm(bb) <= 1e-10
+
+
 def test_exact_breakdown_small_system():
     """n = 12 < m: GMRES terminates in at most n steps with a lucky breakdown."""
     A = P.conv_diff(2, 3, 5.0, (1.0, 0.0))
