@@ -13,9 +13,11 @@
  *
  * Conventions for every entry point:
  *  - Pointers are HIP device pointers owned by the caller unless the
- *    parameter name ends in _host.  The library never calls hipMalloc,
- *    hipFree or any allocating routine on the device; every device buffer is
- *    passed in.  (Host-side handles are allocated with malloc/new.)
+ *    parameter name ends in _host.  The library never calls hipMalloc or
+ *    hipFree: every device buffer holding data is passed in.  (Host-side
+ *    handles are allocated with malloc/new; gmresir_solve on systems of at
+ *    most 2^18 rows records its inner cycle as a HIP graph, and profiling
+ *    creates HIP events -- runtime objects the HIP runtime backs itself.)
  *  - Work is enqueued on the caller's `stream` (a hipStream_t passed as
  *    void*; NULL is the legacy default stream).  Functions that return host
  *    values synchronise that stream before returning.
@@ -144,7 +146,10 @@ size_t gmresir_workspace_bytes(const gmresir_matrix* A, const gmresir_params* p)
    hist_host (may be NULL): receives up to hist_cap per-iteration values
    |g_{j+1}| / |g_1|, the implicit residual of each inner iteration relative
    to the right-hand side of its cycle.  The stream is synchronised once per
-   refinement.  b = 0 gives x = 0 and GMRESIR_OK. */
+   refinement.  b = 0 gives x = 0 and GMRESIR_OK.  For n <= 2^18 (and
+   profile = 0) the kernels of one inner cycle are recorded once as a HIP
+   graph and replayed for every later cycle of the same length (the same
+   kernels and bits as direct launches; less host launch work). */
 int gmresir_solve(const gmresir_matrix* A, const double* b, double* x, const gmresir_params* p,
                   const double* poly_roots_host, void* ws, size_t ws_bytes, gmresir_result* res_host,
                   double* hist_host, int64_t hist_cap, void* stream);
