@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-parameter variant")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--max-iters", type=int, default=1_000_000,
                     help="cap on inner iterations of the timed solves (short hardware-counter runs only)")
@@ -207,6 +208,40 @@ def main():
         "sol_err_vs_u": sol_err,
     }
 
+    if not args.no_learned and os.path.exists(os.path.join(ROOT, "paper_2109_01232_amd", "chooser_weights.json")):
+        # the learned-parameter variant: features -> network -> (m, inner cap,
+        # polynomial degree), then the solve; the timed step includes the
+        # features, the network and the polynomial set-up
+        from paper_2109_01232_amd import chooser as CH
+
+        net = CH.Chooser.load()
+
+        def learned_step():
+            feats = B.gmresir_features(M, b, ws=ws)
+            m_c, capm, deg = net.choose(feats)
+            roots = B.gmresir_poly_setup(M, deg, seed=12345, ws=ws) if deg > 0 else None
+            pc = B.make_params(restart=m_c, inner="fp32", rtol=1e-10, inner_cap=m_c * capm, poly_degree=deg,
+                               check_mode=1)
+            x.zero_()
+            st, d, _ = B.gmresir_solve(M, b, x, pc, poly_roots=roots, ws=ws)
+            return (m_c, capm, deg), st, d
+
+        learned_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            cfg_l, st_l, d_l = learned_step()
+        torch.cuda.synchronize()
+        t_l = (time.perf_counter() - t0) / args.steps
+        xs_l = x.cpu().numpy()
+        true_l = float(np.linalg.norm(system.b - A.scipy() @ xs_l) / np.linalg.norm(system.b))
+        log(f"learned {cfg_l}: {t_l:.4f} s/solve iters={d_l['iters']} resid={true_l:.3e}")
+        out["learned"] = {"s": t_l, "config": {"restart": cfg_l[0], "inner_cap": cfg_l[0] * cfg_l[1],
+                                               "poly_degree": cfg_l[2]},
+                          "iters": d_l["iters"], "status": B.status_string(st_l), "rel_resid_true": true_l,
+                          "speedup_vs_default_ir": t_ir / t_l,
+                          "includes": "features + network + polynomial set-up + solve"}
+
     if not args.no_fp64:
         run(p_64)
         torch.cuda.synchronize()
@@ -221,6 +256,8 @@ def main():
         out["fp64_iters"] = d_64["iters"]
         out["fp64_rel_resid_true"] = d_64["rel_resid_true"]
         out["speedup_vs_fp64"] = t_64 / t_ir
+        if "learned" in out:
+            out["learned"]["speedup_vs_fp64"] = t_64 / out["learned"]["s"]
 
     if not args.no_profile:
         # one more solve with HIP events around every kernel (on the solve's stream)
