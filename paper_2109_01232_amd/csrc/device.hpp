@@ -120,6 +120,12 @@ struct Csr {
   const int* col;
   const void* vals;
   const int* tile_row;  // ntiles+1 row boundaries
+  // sliced ELLPACK copy (sell != 0): slice s holds entries sptr[s] .. sptr[s+1]
+  int sell;
+  int nslices;
+  const int* sptr;
+  const int* scol;
+  const void* svals;  // element type MT, like vals
 };
 
 // Dynamic LDS of a kernel (sized at launch: the SpMV product buffer holds the

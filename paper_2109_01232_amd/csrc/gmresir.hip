@@ -34,6 +34,13 @@ struct gmresir_matrix {
   int32_t* tile_row;
   int ntiles;
   int lds_nnz;  // largest nonzero count of a tile that is staged in LDS (<= TILE_NNZ)
+  // sliced ELLPACK copy (used by the SpMV kernels when present)
+  bool sell;
+  int nslices;
+  int32_t* sell_ptr;
+  int32_t* sell_col;
+  float* sell_v32;
+  double* sell_v64;
   int device;
 };
 
@@ -100,14 +107,12 @@ int grid_rows(const void* kern, int64_t n, int threads = BLOCK) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, want));
 }
 
-// Plain SpMV kernels take one tile per block (blocks beyond the resident ones
-// start as others finish, which balances tiles of unequal cost: measured 4.4
-// vs 3.7 TB/s on the 7-point 150^3 polynomial steps).  Kernels that leave
-// per-block partial sums run one resident wave of blocks (at most MAX_GRID),
-// each over a contiguous range of tiles, which amortises their prologue and
-// partial sums (measured: one tile per block 17 % slower on the 5-point
-// 1000^2 system, 2048 blocks 10 % slower on the 27-point 128^3 system).
-int grid_tiles(int ntiles) { return std::max(1, ntiles); }
+// Row-tiled CSR kernels that leave per-block partial sums run one resident
+// wave of blocks (at most MAX_GRID), each over a contiguous range of tiles,
+// which amortises their prologue and partial sums (measured: one tile per
+// block 17 % slower on the 5-point 1000^2 system, 2048 blocks 10 % slower on
+// the 27-point 128^3 system).  Kernels without partials take one tile per
+// block (grid_spmv).
 int grid_tiles_part(const void* kern, int ntiles, size_t smem) {
   return std::max(1, std::min(resident_grid(kern, smem), ntiles));
 }
@@ -120,7 +125,23 @@ Csr csr_of(const gmresir_matrix* A, bool fp64) {
   c.col = A->colidx;
   c.vals = fp64 ? (const void*)A->vals64 : (const void*)A->vals32;
   c.tile_row = A->tile_row;
+  c.sell = A->sell ? 1 : 0;
+  c.nslices = A->nslices;
+  c.sptr = A->sell_ptr;
+  c.scol = A->sell_col;
+  c.svals = fp64 ? (const void*)A->sell_v64 : (const void*)A->sell_v32;
   return c;
+}
+
+// Grid of an SpMV kernel without partial sums: one tile per block, or four
+// slices (one per wave) per block.
+int grid_spmv(const gmresir_matrix* A) {
+  return A->sell ? std::max(1, (A->nslices + NWAVES - 1) / NWAVES) : std::max(1, A->ntiles);
+}
+// Grid of an SpMV kernel leaving per-block partial sums: one resident wave of
+// blocks at most.
+int grid_spmv_part(const gmresir_matrix* A, const void* kern, size_t smem) {
+  return std::max(1, std::min(resident_grid(kern, smem), A->sell ? (A->nslices + NWAVES - 1) / NWAVES : A->ntiles));
 }
 
 // ---------------------------------------------------------------------------
@@ -457,8 +478,9 @@ struct Ctx {
     A64 = csr_of(A, true);
   }
 
-  size_t lds_in() const { return (size_t)A->lds_nnz * sizeof(T); }   // SpMV products, inner precision
-  size_t lds_64() const { return (size_t)A->lds_nnz * sizeof(double); }
+  // LDS of the tiled SpMV products (none for the sliced ELLPACK kernels)
+  size_t lds_in() const { return A->sell ? 0 : (size_t)A->lds_nnz * sizeof(T); }
+  size_t lds_64() const { return A->sell ? 0 : (size_t)A->lds_nnz * sizeof(double); }
   double sT() const { return (double)sizeof(T); }
   double sS() const { return (double)sizeof(S); }
   double spmv_bytes() const { return (sT() + 4.0) * A->nnz + 4.0 * (A->n + 1); }
@@ -500,11 +522,11 @@ struct Ctx {
                  (write_v ? sS() * n : 0.0);
       if (scaled && ps.x == PB_SRC) {
         auto kern = k_poly_step<T, S, true>;
-        int g = grid_tiles(Ain.ntiles);
+        int g = grid_spmv(A);
         prof->launch(cat, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, write_v, W, w_scaled, y_out, D, cf, st, check_done, (const T*)norm_part(), nB);
       } else {
         auto kern = k_poly_step<T, S, false>;
-        int g = grid_tiles(Ain.ntiles);
+        int g = grid_spmv(A);
         prof->launch(cat, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, 0, W, w_scaled, y_out, D, cf, st, check_done, (const T*)norm_part(), nB);
       }
     }
@@ -520,13 +542,23 @@ struct Ctx {
   template <int SLOTS, bool SCALED>
   void launch_spmv_proj(const T* src, int j, int kmax, int nB) {
     constexpr int KMAX = NWAVES * SLOTS;
-    auto kern = k_spmv_proj<T, S, SLOTS, SCALED>;
-    int g = grid_tiles_part((const void*)kern, Ain.ntiles, lds_in());
     const int C = std::min(j + 1, KMAX);
     // basis columns read from memory: all handled columns but the new one (SCALED)
     const int nread = SCALED ? std::min(j, C) : C;
     double b = spmv_bytes() + sT() * n * 2 + sS() * n * nread + (SCALED ? sS() * n : 0.0);
-    prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, src, V, L.ldv, j, w1, st, part, (const T*)norm_part(), nB);
+    int g;
+    if (A->sell) {
+      auto kern = k_spmv_proj_sell<T, S, SLOTS, SCALED>;
+      constexpr int SPS = (sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS) / SELL_C;  // slices per stage
+      g = std::max(1, std::min(resident_grid((const void*)kern, 0), (A->nslices + SPS - 1) / SPS));
+      prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(BLOCK), 0, stream, Ain, src, V, L.ldv, j, w1, st,
+                   part, (const T*)norm_part(), nB);
+    } else {
+      auto kern = k_spmv_proj<T, S, SLOTS, SCALED>;
+      g = grid_tiles_part((const void*)kern, Ain.ntiles, lds_in());
+      prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, src, V, L.ldv, j, w1,
+                   st, part, (const T*)norm_part(), nB);
+    }
     auto tail = k_reduce_h1_givens<T>;
     const int tg = (C + NWAVES - 1) / NWAVES + (j > 0 ? 1 : 0);
     prof->launch(GMRESIR_CAT_TAIL, 0.0, tail, dim3(tg), dim3(BLOCK), 0, stream, (const T*)part, C, g, (const T*)norm_part(), nB, st, j - 1, kmax);
@@ -712,7 +744,7 @@ struct Ctx {
 
   void resid64(const double* x, const double* b) {
     auto kern = k_resid64;
-    int g = grid_tiles_part((const void*)kern, A64.ntiles, lds_64());
+    int g = grid_spmv_part(A, (const void*)kern, lds_64());
     prof->launch(GMRESIR_CAT_REFINE, 12.0 * A->nnz + 4.0 * (A->n + 1) + 8.0 * n * 3, kern, dim3(g), dim3(BLOCK), lds_64(), stream, A64, x, b, r64, (double*)part);
     sqrt_tail(g, &st.hdr->gamma);
   }
@@ -750,7 +782,7 @@ struct Ctx {
 
   void inner_resid() {
     auto kern = k_inner_resid<T>;
-    int g = grid_tiles_part((const void*)kern, Ain.ntiles, lds_in());
+    int g = grid_spmv_part(A, (const void*)kern, lds_in());
     prof->launch(GMRESIR_CAT_REFINE, spmv_bytes() + sT() * n * 3, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, (const T*)u, (const T*)rhat, wtmp, part);
     cycle_tail(g);
   }
@@ -987,9 +1019,14 @@ const char* gmresir_status_string(int status) {
   }
 }
 
+// storage: fp32 CSR values | tile table | SELL slice pointers | SELL columns |
+// SELL fp32 values | SELL fp64 values (the SELL part sized for its bound)
 size_t gmresir_matrix_storage_bytes(int64_t n, int64_t nnz) {
   if (n < 1 || nnz < 0 || nnz >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31)) return 0;
-  return align_up((size_t)nnz * 4) + align_up((size_t)(max_tiles(n, nnz) + 1) * 4);
+  const size_t E = (size_t)sell_max_entries(n, nnz);
+  const size_t ns = (size_t)((n + SELL_C - 1) / SELL_C);
+  return align_up((size_t)nnz * 4) + align_up((size_t)(max_tiles(n, nnz) + 1) * 4) + align_up((ns + 1) * 4) +
+         align_up(E * 4) + align_up(E * 4) + align_up(E * 8);
 }
 
 int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx, const double* vals,
@@ -1051,8 +1088,38 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
     hipLaunchKernelGGL(k_cast_vals, dim3(g), dim3(BLOCK), 0, s, nnz, vals, v32);
     HIP_TRY(hipGetLastError());
   }
+  // sliced ELLPACK copy, if compact
+  const int64_t ns = (n + SELL_C - 1) / SELL_C;
+  std::vector<int32_t> sptr(ns + 1, 0);
+  bool sell = nnz > 0;
+  for (int64_t sl = 0; sl < ns && sell; ++sl) {
+    int64_t K = 0;
+    for (int64_t r = sl * SELL_C; r < std::min<int64_t>(n, (sl + 1) * SELL_C); ++r) K = std::max<int64_t>(K, rp[r + 1] - rp[r]);
+    if (K > SELL_MAX_ROW) sell = false;
+    const int64_t next = (int64_t)sptr[sl] + SELL_C * K;
+    if (next > sell_max_entries(n, nnz)) sell = false;
+    else sptr[sl + 1] = (int32_t)next;
+  }
+  const size_t E = (size_t)sell_max_entries(n, nnz);
+  char* sbase = st + align_up((size_t)nnz * 4) + align_up((size_t)(max_tiles(n, nnz) + 1) * 4);
+  int32_t* d_sptr = (int32_t*)sbase;
+  int32_t* d_scol = (int32_t*)(sbase + align_up((ns + 1) * 4));
+  float* d_sv32 = (float*)((char*)d_scol + align_up(E * 4));
+  double* d_sv64 = (double*)((char*)d_sv32 + align_up(E * 4));
+  if (sell) {
+    HIP_TRY(hipMemcpyAsync(d_sptr, sptr.data(), (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_build_sell, dim3((unsigned)ns), dim3(SELL_C), 0, s, (int)n, rowptr, colidx, vals, d_sptr,
+                       d_scol, d_sv32, d_sv64);
+    HIP_TRY(hipGetLastError());
+  }
   HIP_TRY(hipStreamSynchronize(s));
   gmresir_matrix* A = new gmresir_matrix;
+  A->sell = sell;
+  A->nslices = (int)ns;
+  A->sell_ptr = d_sptr;
+  A->sell_col = d_scol;
+  A->sell_v32 = d_sv32;
+  A->sell_v64 = d_sv64;
   A->n = n;
   A->nnz = nnz;
   A->rowptr = rowptr;
@@ -1089,13 +1156,13 @@ int gmresir_spmv(const gmresir_matrix* A, int32_t prec, const void* x, void* y, 
   hipStream_t s = (hipStream_t)stream;
   if (prec == GMRESIR_FP64) {
     auto kern = k_spmv<double>;
-    const size_t smem = (size_t)A->lds_nnz * sizeof(double);
-    int g = grid_tiles(A->ntiles);
+    const size_t smem = A->sell ? 0 : (size_t)A->lds_nnz * sizeof(double);
+    int g = grid_spmv(A);
     hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), smem, s, csr_of(A, true), (const double*)x, (double*)y);
   } else if (prec == GMRESIR_FP32) {
     auto kern = k_spmv<float>;
-    const size_t smem = (size_t)A->lds_nnz * sizeof(float);
-    int g = grid_tiles(A->ntiles);
+    const size_t smem = A->sell ? 0 : (size_t)A->lds_nnz * sizeof(float);
+    int g = grid_spmv(A);
     hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), smem, s, csr_of(A, false), (const float*)x, (float*)y);
   } else {
     set_error("gmresir_spmv: prec must be FP64 or FP32");

@@ -24,6 +24,17 @@ constexpr int TILE_ROWS = 512;
 constexpr int TILE_NNZ = 2560;
 constexpr int SPMV_UNROLL = 5;  // nonzeros per thread whose loads are issued together
 
+// Sliced ELLPACK copy of the matrix used by the SpMV kernels when it stays
+// compact: slices of SELL_C = 64 rows (one wave, one row per lane), entry k
+// of row 64 s + l at sell_ptr[s] + 64 k + l; padding entries point at the row
+// itself with value 0 and are skipped by the row length.  Built when no row
+// is longer than SELL_MAX_ROW and the padded size fits sell_max_entries;
+// otherwise the row-tiled CSR kernels run.
+constexpr int SELL_C = 64;
+constexpr int SELL_MAX_ROW = 512;
+constexpr int SELL_UNROLL = 5;  // entries per lane whose loads are issued together
+inline int64_t sell_max_entries(int64_t n, int64_t nnz) { return nnz + nnz / 4 + (n < 4096 ? n : 4096) * 4; }
+
 // Upper bound of the number of tiles (every tile holds at least one row).
 inline int64_t max_tiles(int64_t n, int64_t nnz) {
   (void)nnz;

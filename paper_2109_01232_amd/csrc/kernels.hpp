@@ -75,6 +75,55 @@ __device__ __forceinline__ void stage_products(const Csr& A, int p0, int len, co
   }
 }
 
+// One row of the sliced ELLPACK copy, summed in column order by the lane that
+// owns it (the same order, and so the same bits, as the tiled CSR kernels).
+// Loads of SELL_UNROLL entries are issued before their gathers; padding
+// entries past the row length are loaded (valid addresses) but not added.
+template <typename T, typename XF>
+__device__ __forceinline__ T sell_row(const Csr& A, const XF& xf, int s, int r, int lane) {
+#pragma clang fp contract(off)
+  const T* vals = (const T*)A.svals;
+  const int len = r < A.n ? A.rowptr[r + 1] - A.rowptr[r] : 0;
+  const int base = A.sptr[s];
+  const int K = (A.sptr[s + 1] - base) / SELL_C;
+  T sum = T(0);
+  for (int k0 = 0; k0 < K; k0 += SELL_UNROLL) {
+    int cc[SELL_UNROLL];
+    T vv[SELL_UNROLL], xv[SELL_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SELL_UNROLL; ++u) {
+      const int k = k0 + u < K ? k0 + u : K - 1;
+      cc[u] = A.scol[base + SELL_C * k + lane];
+      vv[u] = vals[base + SELL_C * k + lane];
+    }
+#pragma unroll
+    for (int u = 0; u < SELL_UNROLL; ++u) xv[u] = xf(cc[u]);
+#pragma unroll
+    for (int u = 0; u < SELL_UNROLL; ++u) {
+      const T p = vv[u] * xv[u];
+      if (k0 + u < len) sum = sum + p;
+    }
+  }
+  return sum;
+}
+
+// SpMV over the sliced ELLPACK copy: the block takes a contiguous range of
+// slices, its waves take every fourth of them, each lane one row; epi(r, y)
+// per row as in spmv_tiles.
+template <typename T, typename XF, typename EPI>
+__device__ __forceinline__ void sell_rows(const Csr& A, const XF& xf, EPI& epi) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int B = gridDim.x, lb = logical_block();
+  const int s0 = (int)((long)A.nslices * lb / B);
+  const int s1 = (int)((long)A.nslices * (lb + 1) / B);
+  for (int s = s0 + wid; s < s1; s += NWAVES) {
+    const int r = s * SELL_C + lane;
+    const T y = sell_row<T>(A, xf, s, r, lane);
+    if (r < A.n) epi(r, y);
+  }
+}
+
 // Row-tiled CSR SpMV: a block takes a contiguous range of tiles; per tile the
 // nonzeros are streamed with coalesced loads, multiplied by the gathered x and
 // staged in LDS, then each thread sums one row in column order.  epi(r, y) is
@@ -400,6 +449,73 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict_
     __syncthreads();  // y staged; prod free for the next tile
   }
   if (end > base) project_rows<T, S, SLOTS, SCALED>(V, ldv, j, C, base, end - base, ys, vs, acc, lane, wid);
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) {
+    const int c = wid + NWAVES * q;
+    if (c < C) {
+      const T v = wave_sum(acc[q]);
+      if (lane == 0) s_vals[c] = v;
+    }
+  }
+  __syncthreads();
+  store_partials(s_vals, C, part);
+}
+
+// The same over the sliced ELLPACK copy: a block takes a contiguous range of
+// stages of STAGE rows (16 slices in fp32, 8 in fp64); per stage each wave
+// sums its slices' rows (one row per lane), stores w and v_j and stages them
+// in LDS, then the block projects the stage's rows as above.
+template <typename T, typename S, int SLOTS, bool SCALED>
+__global__ __launch_bounds__(BLOCK) void k_spmv_proj_sell(Csr A, const T* __restrict__ src, S* __restrict__ V,
+                                                          long ldv, int j, T* __restrict__ w_out, State st,
+                                                          T* __restrict__ part, const T* __restrict__ norm_part,
+                                                          int nB) {
+  if (st.hdr->flags & F_DONE) return;
+  constexpr int KMAX = NWAVES * SLOTS;
+  constexpr int STAGE = sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS;
+  constexpr int SPS = STAGE / SELL_C;  // slices per stage
+  __shared__ T ys[STAGE];
+  __shared__ T vs[STAGE];
+  __shared__ T s_vals[KMAX];
+  const T inv = SCALED ? prev_inv_norm<T>(st, norm_part, nB) : T(1);
+  const XScaled<T, S> xs{src, inv};
+  const int C = (j + 1 < KMAX) ? j + 1 : KMAX;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  T acc[SLOTS];
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) acc[q] = T(0);
+  const int nstages = (A.nslices + SPS - 1) / SPS;
+  const int B = gridDim.x, lb = logical_block();
+  const int g0 = (int)((long)nstages * lb / B);
+  const int g1 = (int)((long)nstages * (lb + 1) / B);
+  for (int g = g0; g < g1; ++g) {
+    for (int i = wid; i < SPS; i += NWAVES) {
+      const int sl = g * SPS + i;
+      const int r = sl * SELL_C + lane;
+      T y = T(0), vj = T(0);
+      if (sl < A.nslices) {
+        if (SCALED) y = sell_row<T>(A, xs, sl, r, lane);
+        else y = sell_row<T>(A, XPlain<T>{src}, sl, r, lane);
+        if (r < A.n) {
+          w_out[r] = y;
+          if (SCALED) {
+            vj = xs(r);
+            Basis<S, T>::store(V + (size_t)j * ldv + r, vj);
+          }
+        } else {
+          y = T(0);
+        }
+      }
+      ys[i * SELL_C + lane] = y;
+      if (SCALED) vs[i * SELL_C + lane] = vj;
+    }
+    __syncthreads();
+    const int base = g * STAGE;
+    const int nrows = A.n - base < STAGE ? A.n - base : STAGE;
+    project_rows<T, S, SLOTS, SCALED>(V, ldv, j, C, base, nrows, ys, vs, acc, lane, wid);
+    __syncthreads();
+  }
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q) {
     const int c = wid + NWAVES * q;
@@ -889,7 +1005,8 @@ __global__ __launch_bounds__(BLOCK) void k_resid64(Csr A, const double* __restri
   double* prod = dyn_lds<double>();  // one entry per nonzero of the largest tile
   __shared__ double s_vals[1], s_scr[NWAVES * WAVE];
   ResidEpi epi{b, r, 0.0};
-  spmv_tiles<double>(A, XPlain<double>{x}, epi, prod, s_scr);
+  if (A.sell) sell_rows<double>(A, XPlain<double>{x}, epi);
+  else spmv_tiles<double>(A, XPlain<double>{x}, epi, prod, s_scr);
   const double bs = block_sum(epi.nrm, s_scr);
   if (threadIdx.x == 0) s_vals[0] = bs;
   __syncthreads();
@@ -959,7 +1076,8 @@ __global__ __launch_bounds__(BLOCK) void k_inner_resid(Csr A, const T* __restric
   T* prod = dyn_lds<T>();  // one entry per nonzero of the largest tile
   __shared__ T s_vals[1], s_scr[NWAVES * WAVE];
   InnerResidEpi<T> epi{rhat, wtmp, T(0)};
-  spmv_tiles<T>(A, XPlain<T>{u}, epi, prod, s_scr);
+  if (A.sell) sell_rows<T>(A, XPlain<T>{u}, epi);
+  else spmv_tiles<T>(A, XPlain<T>{u}, epi, prod, s_scr);
   const T bs = block_sum(epi.nrm, s_scr);
   if (threadIdx.x == 0) s_vals[0] = bs;
   __syncthreads();
@@ -1102,10 +1220,13 @@ __global__ __launch_bounds__(BLOCK) void k_poly_step(Csr A, const T* __restrict_
   epi.Y = Y;
   epi.D = D;
   epi.cf = cf;
-  if (SCALED)
-    spmv_tiles<T>(A, XScaled<T, S>{src, epi.inv}, epi, prod, s_scr);
-  else
-    spmv_tiles<T>(A, XPlain<T>{src}, epi, prod, s_scr);
+  if (SCALED) {
+    if (A.sell) sell_rows<T>(A, XScaled<T, S>{src, epi.inv}, epi);
+    else spmv_tiles<T>(A, XScaled<T, S>{src, epi.inv}, epi, prod, s_scr);
+  } else {
+    if (A.sell) sell_rows<T>(A, XPlain<T>{src}, epi);
+    else spmv_tiles<T>(A, XPlain<T>{src}, epi, prod, s_scr);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1123,12 +1244,38 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(Csr A, const T* __restrict__ x, 
   T* prod = dyn_lds<T>();  // one entry per nonzero of the largest tile
   __shared__ T s_scr[NWAVES * WAVE];
   PlainEpi<T> epi{y};
-  spmv_tiles<T>(A, XPlain<T>{x}, epi, prod, s_scr);
+  if (A.sell) sell_rows<T>(A, XPlain<T>{x}, epi);
+  else spmv_tiles<T>(A, XPlain<T>{x}, epi, prod, s_scr);
 }
 
 __global__ void k_cast_vals(int64_t nnz, const double* __restrict__ v64, float* __restrict__ v32) {
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * BLOCK)
     v32[i] = (float)v64[i];
+}
+
+// Fill the sliced ELLPACK copy (one block of 64 threads per slice, one row per
+// thread); fp32 values rounded to nearest even like the CSR copy.
+__global__ void k_build_sell(int n, const int* __restrict__ rowptr, const int* __restrict__ colidx,
+                             const double* __restrict__ vals, const int* __restrict__ sptr, int* __restrict__ scol,
+                             float* __restrict__ sv32, double* __restrict__ sv64) {
+  const int sl = blockIdx.x, lane = threadIdx.x;
+  const int r = sl * SELL_C + lane;
+  const int base = sptr[sl];
+  const int K = (sptr[sl + 1] - base) / SELL_C;
+  const int p0 = r < n ? rowptr[r] : 0;
+  const int len = r < n ? rowptr[r + 1] - p0 : 0;
+  for (int k = 0; k < K; ++k) {
+    const int e = base + SELL_C * k + lane;
+    int c = r < n ? r : 0;
+    double v = 0.0;
+    if (k < len) {
+      c = colidx[p0 + k];
+      v = vals[p0 + k];
+    }
+    scol[e] = c;
+    sv64[e] = v;
+    sv32[e] = (float)v;
+  }
 }
 
 // v[i] = 2 * (splitmix64(seed ^ i) >> 11) * 2^-53 - 1 (SplitMix64, S. Vigna).
