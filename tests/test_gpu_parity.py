@@ -305,6 +305,32 @@ def test_ragged_rows_every_basis_width(m, inner, basis):
     assert np.linalg.norm(bb - A.scipy() @ x.cpu().numpy()) / np.linalg.norm(bb) <= 1e-10
 
 
+def test_row_tiled_path_solve():
+    """A row longer than the sliced-ELLPACK limit (512) keeps the matrix on
+    the row-tiled CSR kernels (LDS-staged products, block-reduced long row):
+    fp32 IR and fp64 GMRES against the oracle on such a system."""
+    A0 = P.conv_diff(2, 40, 20.0, (1.0, 0.3))
+    S = A0.scipy().tolil()
+    cols = np.arange(0, A0.n, 2)[:700]
+    S[5, cols] = S[5, cols].toarray() + 1e-3  # a 700-entry row, still diagonally dominant
+    S = S.tocsr()
+    S.sort_indices()
+    A = P.CSR(A0.n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+    u = np.random.default_rng(11).uniform(-1, 1, A.n)
+    bb = S @ u
+    M = B.Matrix.from_csr(A)
+    b = dev_tensor(bb)
+    for inner in ("fp32", "fp64"):
+        say("row-tiled solve", inner)
+        x, d, h = B.solve(M, b, restart=30, inner=inner, rtol=1e-10, check_mode=0, hist_cap=20000)
+        ref = (L.gmres(A, bb, m=30, rtol=1e-10, check_mode=0, max_iters=30) if inner == "fp64" else
+               L.gmres_ir(A, bb, m=30, rtol=1e-10, inner="fp32", check_mode=0, max_iters=30))
+        tol = 1e-10 if inner == "fp64" else HIST_TOL_FP32
+        assert np.max(np.abs(h[:30] - np.array(ref.hist[:30]))) <= tol
+        assert d["status"] == B.OK
+        assert np.linalg.norm(bb - S @ x.cpu().numpy()) / np.linalg.norm(bb) <= 1e-10
+
+
 def test_exact_breakdown_small_system():
     """n = 12 < m: GMRES terminates in at most n steps with a lucky breakdown."""
     A = P.conv_diff(2, 3, 5.0, (1.0, 0.0))
