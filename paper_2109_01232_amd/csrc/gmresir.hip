@@ -479,7 +479,8 @@ struct Ctx {
   }
 
   // LDS of the tiled SpMV products (none for the sliced ELLPACK kernels)
-  size_t lds_in() const { return A->sell ? 0 : (size_t)A->lds_nnz * sizeof(T); }
+  size_t lds_tiled() const { return (size_t)A->lds_nnz * sizeof(T); }
+  size_t lds_in() const { return A->sell ? 0 : lds_tiled(); }
   size_t lds_64() const { return A->sell ? 0 : (size_t)A->lds_nnz * sizeof(double); }
   double sT() const { return (double)sizeof(T); }
   double sS() const { return (double)sizeof(S); }
@@ -547,7 +548,9 @@ struct Ctx {
     const int nread = SCALED ? std::min(j, C) : C;
     double b = spmv_bytes() + sT() * n * 2 + sS() * n * nread + (SCALED ? sS() * n : 0.0);
     int g;
-    if (A->sell) {
+    // small systems (under 64 K rows) keep the tiled kernel, whose 512-row
+    // tiles give more blocks than the 1024-row stages
+    if (A->sell && A->nslices >= 1024) {
       auto kern = k_spmv_proj_sell<T, S, SLOTS, SCALED>;
       constexpr int SPS = (sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS) / SELL_C;  // slices per stage
       g = std::max(1, std::min(resident_grid((const void*)kern, 0), (A->nslices + SPS - 1) / SPS));
@@ -555,9 +558,9 @@ struct Ctx {
                    part, (const T*)norm_part(), nB);
     } else {
       auto kern = k_spmv_proj<T, S, SLOTS, SCALED>;
-      g = grid_tiles_part((const void*)kern, Ain.ntiles, lds_in());
-      prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, src, V, L.ldv, j, w1,
-                   st, part, (const T*)norm_part(), nB);
+      g = grid_tiles_part((const void*)kern, Ain.ntiles, lds_tiled());
+      prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(BLOCK), lds_tiled(), stream, Ain, src, V, L.ldv, j,
+                   w1, st, part, (const T*)norm_part(), nB);
     }
     auto tail = k_reduce_h1_givens<T>;
     const int tg = (C + NWAVES - 1) / NWAVES + (j > 0 ? 1 : 0);
