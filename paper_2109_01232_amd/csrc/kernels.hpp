@@ -644,6 +644,19 @@ __global__ __launch_bounds__(WV * WAVE) void k_update_proj(int n, const T* __res
     using P = Packed<S, T, R>;
     typename P::type vr[SLOTS];
     T s[R];
+    // narrow bases: w's load goes out with V's, before the barrier (with few
+    // columns the step is otherwise two dependent memory round trips); wide
+    // ones load it after the barrier to keep registers for V
+    constexpr bool W_EARLY = SLOTS <= 4;
+    T wv[R];
+    if constexpr (W_EARLY) {
+      if (nv > 0) {
+        load_vec<T, R>(w_in + r, wv);
+      } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i) wv[i] = T(0);
+      }
+    }
 #pragma unroll
     for (int i = 0; i < R; ++i) s[i] = T(0);
 #pragma unroll
@@ -658,12 +671,13 @@ __global__ __launch_bounds__(WV * WAVE) void k_update_proj(int n, const T* __res
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) P::hold(vr[q]);
-    T wv[R];
-    if (nv > 0) {
-      load_vec<T, R>(w_in + r, wv);
-    } else {
+    if constexpr (!W_EARLY) {
+      if (nv > 0) {
+        load_vec<T, R>(w_in + r, wv);
+      } else {
 #pragma unroll
-      for (int i = 0; i < R; ++i) wv[i] = T(0);
+        for (int i = 0; i < R; ++i) wv[i] = T(0);
+      }
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
