@@ -948,8 +948,23 @@ __global__ __launch_bounds__(BLOCK) void k_backsolve(State st) {
   const bool in_lds = (size_t)k * (k + 1) / 2 * sizeof(T) <= 40960;
   for (int i = threadIdx.x; i < k; i += BLOCK) s_g[i] = (T)st.g[i];
   if (in_lds) {
-    for (int c = 0; c < k; ++c)
-      for (int i = threadIdx.x; i <= c; i += BLOCK) s_R[(size_t)c * (c + 1) / 2 + i] = (T)st.R[(size_t)c * ld + i];
+    // the k columns as one flat range, four loads per thread in flight
+    // (column by column the loads would wait for each other)
+    const int tot = k * ld;
+    for (int i0 = 0; i0 < tot; i0 += 4 * BLOCK) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int id = i0 + threadIdx.x + u * BLOCK;
+        v[u] = id < tot ? st.R[id] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int id = i0 + threadIdx.x + u * BLOCK;
+        const int c = id / ld, i = id - c * ld;
+        if (id < tot && i <= c) s_R[(size_t)c * (c + 1) / 2 + i] = (T)v[u];
+      }
+    }
   }
   __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
