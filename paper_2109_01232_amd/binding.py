@@ -82,6 +82,7 @@ _SIGS = {
     "gmresir_matrix_n": (_i64, [_vp]),
     "gmresir_matrix_nnz": (_i64, [_vp]),
     "gmresir_matrix_tiles": (_i64, [_vp]),
+    "gmresir_matrix_layout": (_i32, [_vp]),
     "gmresir_spmv": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "gmresir_workspace_bytes": (_sz, [_vp, ctypes.POINTER(Params)]),
     "gmresir_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(Params), _dp, _vp, _sz,
@@ -228,6 +229,12 @@ class Matrix:
     @property
     def tiles(self) -> int:
         return int(lib().gmresir_matrix_tiles(self.handle))
+
+    @property
+    def layout(self) -> int:
+        """0 = CSR row tiles only, 1 = sliced ELLPACK with 32-bit columns,
+        2 = sliced ELLPACK with 16-bit column offsets."""
+        return int(lib().gmresir_matrix_layout(self.handle))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -96,6 +96,12 @@ struct StateHdr {
   uint32_t spare[8];
 };
 
+// The stop flags, read where the call stands: an atomic (relaxed) read is not
+// sunk to its first use, so its round trip overlaps the loads that follow.
+__device__ __forceinline__ int load_flags(const StateHdr* h) {
+  return __hip_atomic_load(&h->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct State {
   StateHdr* hdr;
   double* h1;    // m+1   first-pass projection coefficients (even iterations j)
@@ -124,7 +130,9 @@ struct Csr {
   int sell;
   int nslices;
   const int* sptr;
-  const int* scol;
+  const int* scol;      // column of each entry (d16 == 0)
+  const short* scol16;  // column - row of each entry (d16 != 0; padding 0, rows >= n relative to row 0)
+  int d16;
   const void* svals;  // element type MT, like vals
 };
 

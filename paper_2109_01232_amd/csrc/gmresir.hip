@@ -38,7 +38,8 @@ struct gmresir_matrix {
   bool sell;
   int nslices;
   int32_t* sell_ptr;
-  int32_t* sell_col;
+  int32_t* sell_col;  // 32-bit columns, or (sell_d16) 16-bit offsets from the row in the same region
+  bool sell_d16;
   float* sell_v32;
   double* sell_v64;
   int device;
@@ -129,6 +130,8 @@ Csr csr_of(const gmresir_matrix* A, bool fp64) {
   c.nslices = A->nslices;
   c.sptr = A->sell_ptr;
   c.scol = A->sell_col;
+  c.scol16 = (const short*)A->sell_col;
+  c.d16 = A->sell_d16 ? 1 : 0;
   c.svals = fp64 ? (const void*)A->sell_v64 : (const void*)A->sell_v32;
   return c;
 }
@@ -484,7 +487,12 @@ struct Ctx {
   size_t lds_64() const { return A->sell ? 0 : (size_t)A->lds_nnz * sizeof(double); }
   double sT() const { return (double)sizeof(T); }
   double sS() const { return (double)sizeof(S); }
-  double spmv_bytes() const { return (sT() + 4.0) * A->nnz + 4.0 * (A->n + 1); }
+  // values + column indices (4 bytes, or 2 for the 16-bit offsets of the
+  // sliced copy) + row pointers; sell_path: the launch reads the sliced copy
+  double spmv_bytes(bool sell_path = true) const {
+    const double idx = (sell_path && A->sell && A->sell_d16) ? 2.0 : 4.0;
+    return (sT() + idx) * A->nnz + 4.0 * (A->n + 1);
+  }
 
   T* buf(int b, T* src) {
     switch (b) {
@@ -546,11 +554,12 @@ struct Ctx {
     const int C = std::min(j + 1, KMAX);
     // basis columns read from memory: all handled columns but the new one (SCALED)
     const int nread = SCALED ? std::min(j, C) : C;
-    double b = spmv_bytes() + sT() * n * 2 + sS() * n * nread + (SCALED ? sS() * n : 0.0);
-    int g;
     // small systems (under 64 K rows) keep the tiled kernel, whose 512-row
     // tiles give more blocks than the 1024-row stages
-    if (A->sell && A->nslices >= 1024) {
+    const bool sell_path = A->sell && A->nslices >= 1024;
+    double b = spmv_bytes(sell_path) + sT() * n * 2 + sS() * n * nread + (SCALED ? sS() * n : 0.0);
+    int g;
+    if (sell_path) {
       auto kern = k_spmv_proj_sell<T, S, SLOTS, SCALED>;
       constexpr int SPS = (sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS) / SELL_C;  // slices per stage
       g = std::max(1, std::min(resident_grid((const void*)kern, 0), (A->nslices + SPS - 1) / SPS));
@@ -570,7 +579,7 @@ struct Ctx {
   void reduce_h(int cat, int producer_grid, int nv, double* h) {
     auto kern = k_reduce_cols<T>;
     const int tg = (nv + NWAVES - 1) / NWAVES;
-    prof->launch(cat == GMRESIR_CAT_OTHER ? cat : GMRESIR_CAT_TAIL, 0.0, kern, dim3(tg), dim3(BLOCK), 0, stream, (const T*)part, nv, producer_grid, h, st, 1);
+    prof->launch(cat == GMRESIR_CAT_OTHER ? cat : GMRESIR_CAT_TAIL, 0.0, kern, dim3(tg), dim3(BLOCK), 0, stream, (const T*)part, nv, producer_grid, h);
   }
 
   template <bool SCALED>
@@ -748,7 +757,7 @@ struct Ctx {
   void resid64(const double* x, const double* b) {
     auto kern = k_resid64;
     int g = grid_spmv_part(A, (const void*)kern, lds_64());
-    prof->launch(GMRESIR_CAT_REFINE, 12.0 * A->nnz + 4.0 * (A->n + 1) + 8.0 * n * 3, kern, dim3(g), dim3(BLOCK), lds_64(), stream, A64, x, b, r64, (double*)part);
+    prof->launch(GMRESIR_CAT_REFINE, (A->sell && A->sell_d16 ? 10.0 : 12.0) * A->nnz + 4.0 * (A->n + 1) + 8.0 * n * 3, kern, dim3(g), dim3(BLOCK), lds_64(), stream, A64, x, b, r64, (double*)part);
     sqrt_tail(g, &st.hdr->gamma);
   }
 
@@ -1109,10 +1118,21 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
   int32_t* d_scol = (int32_t*)(sbase + align_up((ns + 1) * 4));
   float* d_sv32 = (float*)((char*)d_scol + align_up(E * 4));
   double* d_sv64 = (double*)((char*)d_sv32 + align_up(E * 4));
+  bool d16 = false;
   if (sell) {
+    // 16-bit column offsets if every entry is within 32767 columns of its row
+    // (the check's flag sits in the column region until the copy is built)
+    int far = 1;
+    HIP_TRY(hipMemsetAsync(d_scol, 0, sizeof(int), s));
+    const int gc = (int)std::min<int64_t>(4096, (n + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_col_offset_check, dim3(gc), dim3(BLOCK), 0, s, (int)n, rowptr, colidx, (int*)d_scol);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&far, d_scol, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    d16 = far == 0;
     HIP_TRY(hipMemcpyAsync(d_sptr, sptr.data(), (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_build_sell, dim3((unsigned)ns), dim3(SELL_C), 0, s, (int)n, rowptr, colidx, vals, d_sptr,
-                       d_scol, d_sv32, d_sv64);
+                       d_scol, (short*)d_scol, d16 ? 1 : 0, d_sv32, d_sv64);
     HIP_TRY(hipGetLastError());
   }
   HIP_TRY(hipStreamSynchronize(s));
@@ -1121,6 +1141,7 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
   A->nslices = (int)ns;
   A->sell_ptr = d_sptr;
   A->sell_col = d_scol;
+  A->sell_d16 = d16;
   A->sell_v32 = d_sv32;
   A->sell_v64 = d_sv64;
   A->n = n;
@@ -1146,6 +1167,7 @@ int gmresir_matrix_destroy(gmresir_matrix* A) {
 int64_t gmresir_matrix_n(const gmresir_matrix* A) { return A ? A->n : -1; }
 int64_t gmresir_matrix_nnz(const gmresir_matrix* A) { return A ? A->nnz : -1; }
 int64_t gmresir_matrix_tiles(const gmresir_matrix* A) { return A ? A->ntiles : -1; }
+int32_t gmresir_matrix_layout(const gmresir_matrix* A) { return A ? (A->sell ? (A->sell_d16 ? 2 : 1) : 0) : -1; }
 
 int gmresir_spmv(const gmresir_matrix* A, int32_t prec, const void* x, void* y, void* stream) {
   if (!A || !x || !y) {

@@ -79,13 +79,15 @@ __device__ __forceinline__ void stage_products(const Csr& A, int p0, int len, co
 // owns it (the same order, and so the same bits, as the tiled CSR kernels).
 // Loads of SELL_UNROLL entries are issued before their gathers; padding
 // entries past the row length are loaded (valid addresses) but not added.
-template <typename T, typename XF>
-__device__ __forceinline__ T sell_row(const Csr& A, const XF& xf, int s, int r, int lane) {
+// D16: the columns are 16-bit offsets from the row (rows past n: from row 0).
+template <typename T, bool D16, typename XF>
+__device__ __forceinline__ T sell_row_cols(const Csr& A, const XF& xf, int s, int r, int lane) {
 #pragma clang fp contract(off)
   const T* vals = (const T*)A.svals;
   const int len = r < A.n ? A.rowptr[r + 1] - A.rowptr[r] : 0;
   const int base = A.sptr[s];
   const int K = (A.sptr[s + 1] - base) / SELL_C;
+  const int rr = r < A.n ? r : 0;
   T sum = T(0);
   for (int k0 = 0; k0 < K; k0 += SELL_UNROLL) {
     int cc[SELL_UNROLL];
@@ -93,7 +95,8 @@ __device__ __forceinline__ T sell_row(const Csr& A, const XF& xf, int s, int r, 
 #pragma unroll
     for (int u = 0; u < SELL_UNROLL; ++u) {
       const int k = k0 + u < K ? k0 + u : K - 1;
-      cc[u] = A.scol[base + SELL_C * k + lane];
+      if constexpr (D16) cc[u] = rr + (int)A.scol16[base + SELL_C * k + lane];
+      else cc[u] = A.scol[base + SELL_C * k + lane];
       vv[u] = vals[base + SELL_C * k + lane];
     }
 #pragma unroll
@@ -105,6 +108,13 @@ __device__ __forceinline__ T sell_row(const Csr& A, const XF& xf, int s, int r, 
     }
   }
   return sum;
+}
+
+// The column width is chosen once per slice (a wave-uniform branch), not per
+// load: a load under a branch is waited for at the branch's end.
+template <typename T, typename XF>
+__device__ __forceinline__ T sell_row(const Csr& A, const XF& xf, int s, int r, int lane) {
+  return A.d16 ? sell_row_cols<T, true>(A, xf, s, r, lane) : sell_row_cols<T, false>(A, xf, s, r, lane);
 }
 
 // SpMV over the sliced ELLPACK copy: the block takes a contiguous range of
@@ -376,7 +386,9 @@ template <typename T, typename S, int SLOTS, bool SCALED>
 __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict__ src, S* __restrict__ V, long ldv,
                                                      int j, T* __restrict__ w_out, State st, T* __restrict__ part,
                                                      const T* __restrict__ norm_part, int nB) {
-  if (st.hdr->flags & F_DONE) return;
+  // the stop flag is read first and tested after the prologue, whose loads
+  // are harmless either way: one memory round trip instead of two
+  const int flags = load_flags(st.hdr);
   constexpr int KMAX = NWAVES * SLOTS;
   // rows staged for one projection pass: several short tiles at once, so
   // the 64 lanes of a wave get whole groups of 4 rows (fp64 keeps 512 rows
@@ -389,6 +401,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict_
   __shared__ T s_red[NWAVES];
   const T* vals = (const T*)A.vals;
   const T inv = SCALED ? prev_inv_norm<T>(st, norm_part, nB) : T(1);
+  if (flags & F_DONE) return;
   const XScaled<T, S> xs{src, inv};
   const int C = (j + 1 < KMAX) ? j + 1 : KMAX;  // columns handled here
   const int lane = threadIdx.x & (WAVE - 1);
@@ -470,7 +483,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj_sell(Csr A, const T* __rest
                                                           long ldv, int j, T* __restrict__ w_out, State st,
                                                           T* __restrict__ part, const T* __restrict__ norm_part,
                                                           int nB) {
-  if (st.hdr->flags & F_DONE) return;
+  const int flags = load_flags(st.hdr);  // tested after the prologue, as above
   constexpr int KMAX = NWAVES * SLOTS;
   constexpr int STAGE = sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS;
   constexpr int SPS = STAGE / SELL_C;  // slices per stage
@@ -478,6 +491,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj_sell(Csr A, const T* __rest
   __shared__ T vs[STAGE];
   __shared__ T s_vals[KMAX];
   const T inv = SCALED ? prev_inv_norm<T>(st, norm_part, nB) : T(1);
+  if (flags & F_DONE) return;
   const XScaled<T, S> xs{src, inv};
   const int C = (j + 1 < KMAX) ? j + 1 : KMAX;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -618,7 +632,7 @@ template <typename T, typename S, int SLOTS, int R, int WV>
 __global__ __launch_bounds__(WV * WAVE) void k_update_proj(int n, const T* __restrict__ w_in, T* __restrict__ w_out,
                                                            const S* __restrict__ V, long ldv, int k, State st,
                                                            T* __restrict__ part) {
-  if (st.hdr->flags & F_DONE) return;
+  const int flags = load_flags(st.hdr);  // tested after h1 is staged (one round trip for both)
   constexpr int KMAX = WV * SLOTS;
   constexpr int STEP = WAVE * R;
   __shared__ T s_h[KMAX];
@@ -627,6 +641,7 @@ __global__ __launch_bounds__(WV * WAVE) void k_update_proj(int n, const T* __res
   const double* h1 = st.h1_of(k - 1);
   for (int c = threadIdx.x; c < KMAX; c += WV * WAVE) s_h[c] = c < k ? (T)h1[c] : T(0);
   __syncthreads();
+  if (flags & F_DONE) return;
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);  // wave-uniform: hq in scalar registers
   T hq[SLOTS], acc[SLOTS];
@@ -824,13 +839,14 @@ template <typename T, typename S>
 __global__ __launch_bounds__(BLOCK) void k_update_norm(int n, const T* __restrict__ w_in, T* __restrict__ wtmp,
                                                        const S* __restrict__ V, long ldv, int j, State st,
                                                        T* __restrict__ part) {
-  if (st.hdr->flags & F_DONE) return;
+  const int flags = load_flags(st.hdr);  // tested after h2 is staged (one round trip for both)
   __shared__ T s_h[MAX_RESTART + 2];
   __shared__ T s_vals[1];
   __shared__ T s_scr[NWAVES * WAVE];
   const int k = j + 1;
   for (int c = threadIdx.x; c < k; c += BLOCK) s_h[c] = (T)st.h2[c];
   __syncthreads();
+  if (flags & F_DONE) return;
   int r0, r1;
   block_rows(n, r0, r1);
   T nrm = T(0);
@@ -869,11 +885,12 @@ __global__ __launch_bounds__(BLOCK) void k_update_norm(int n, const T* __restric
 
 // h[c] = sum of the partials of column c < nv.  Grid ceil(nv / 4): wave w
 // of block b sums column 4 b + w, so the partials are read by many CUs at
-// once (one CU alone is latency bound on them).
+// once (one CU alone is latency bound on them).  It does not test the stop
+// flag: after a cycle has stopped, the h it writes is read by nothing before
+// the next cycle writes it again, and a flag test would put one more memory
+// round trip in front of the reduction.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_reduce_cols(const T* __restrict__ part, int nv, int B, double* h, State st,
-                                                       int check_done) {
-  if (check_done && (st.hdr->flags & F_DONE)) return;
+__global__ __launch_bounds__(BLOCK) void k_reduce_cols(const T* __restrict__ part, int nv, int B, double* h) {
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int c = blockIdx.x * NWAVES + wid;
   if (c >= nv) return;
@@ -889,12 +906,12 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_reduce_h1_givens(const T* __restrict__ part, int nv, int B,
                                                             const T* __restrict__ norm_part, int nB, State st, int jg,
                                                             int kmax) {
-  if (st.hdr->flags & F_DONE) return;
   const int ncb = (nv + NWAVES - 1) / NWAVES;
   if ((int)blockIdx.x < ncb) {
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int c = blockIdx.x * NWAVES + wid;
     if (c >= nv) return;
+    // no flag test here, as in k_reduce_cols
     const T v = wave_reduce_column(part + (size_t)c * MAX_BLOCKS, B);
     if ((threadIdx.x & (WAVE - 1)) == 0) st.h1_of(jg + 1)[c] = (double)v;
     return;
@@ -903,7 +920,9 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_h1_givens(const T* __restrict_
   __shared__ T s_col[MAX_RESTART + 2];
   __shared__ T s_cs[MAX_RESTART];
   __shared__ T s_sn[MAX_RESTART];
+  const int flags = load_flags(st.hdr);  // tested after the partials are in
   reduce_partials(norm_part, 1, nB, s_n);
+  if (flags & F_DONE) return;
   givens_tail<T>(st, jg, kmax, s_n[0], s_col, s_cs, s_sn);
 }
 
@@ -911,12 +930,13 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_h1_givens(const T* __restrict_
 // last iteration of a cycle).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_norm_givens(const T* __restrict__ part, int B, State st, int j, int kmax) {
-  if (st.hdr->flags & F_DONE) return;
+  const int flags = load_flags(st.hdr);  // tested after the partials are in, as above
   __shared__ T s_col[MAX_RESTART + 2];
   __shared__ T s_cs[MAX_RESTART];
   __shared__ T s_sn[MAX_RESTART];
   __shared__ T s_out[1];
   reduce_partials(part, 1, B, s_out);
+  if (flags & F_DONE) return;
   givens_tail<T>(st, j, kmax, s_out[0], s_col, s_cs, s_sn);
 }
 
@@ -1282,26 +1302,45 @@ __global__ void k_cast_vals(int64_t nnz, const double* __restrict__ v64, float* 
     v32[i] = (float)v64[i];
 }
 
+// *flag != 0 if some entry lies more than 32767 columns from its row (then
+// the sliced copy keeps 32-bit columns).  Grid-stride over the rows.
+__global__ void k_col_offset_check(int n, const int* __restrict__ rowptr, const int* __restrict__ colidx, int* flag) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    bool far = false;
+    for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+      const int d = colidx[p] - r;
+      far = far || d > 32767 || d < -32767;
+    }
+    if (far) atomicOr(flag, 1);
+  }
+}
+
 // Fill the sliced ELLPACK copy (one block of 64 threads per slice, one row per
-// thread); fp32 values rounded to nearest even like the CSR copy.
+// thread); fp32 values rounded to nearest even like the CSR copy.  Columns are
+// stored as 32-bit indices, or (d16) as 16-bit offsets from the row, which
+// take a quarter of the SpMV's bytes off (6 instead of 8 per fp32 nonzero).
+// Padding entries point at the row itself (offset 0), rows past n at row 0.
 __global__ void k_build_sell(int n, const int* __restrict__ rowptr, const int* __restrict__ colidx,
                              const double* __restrict__ vals, const int* __restrict__ sptr, int* __restrict__ scol,
-                             float* __restrict__ sv32, double* __restrict__ sv64) {
+                             short* __restrict__ scol16, int d16, float* __restrict__ sv32,
+                             double* __restrict__ sv64) {
   const int sl = blockIdx.x, lane = threadIdx.x;
   const int r = sl * SELL_C + lane;
   const int base = sptr[sl];
   const int K = (sptr[sl + 1] - base) / SELL_C;
   const int p0 = r < n ? rowptr[r] : 0;
   const int len = r < n ? rowptr[r + 1] - p0 : 0;
+  const int rr = r < n ? r : 0;
   for (int k = 0; k < K; ++k) {
     const int e = base + SELL_C * k + lane;
-    int c = r < n ? r : 0;
+    int c = rr;
     double v = 0.0;
     if (k < len) {
       c = colidx[p0 + k];
       v = vals[p0 + k];
     }
-    scol[e] = c;
+    if (d16) scol16[e] = (short)(c - rr);
+    else scol[e] = c;
     sv64[e] = v;
     sv32[e] = (float)v;
   }

@@ -76,11 +76,32 @@ def long_row_matrix(n=8000, seed=1):
     return P.CSR(n, np.array(rowptr, dtype=np.int32), np.concatenate(cols).astype(np.int32), np.concatenate(vals))
 
 
+def far_column_matrix(side=264, seed=2):
+    """2D convection-diffusion on side^2 >= 65473 rows (enough slices for the
+    sliced SpMV + projection kernel) plus one coupling per seventh row to the
+    row n/2 away: columns too far from their rows for 16-bit offsets, so the
+    sliced copy keeps 32-bit columns.  Still diagonally dominant."""
+    import scipy.sparse as sp
+    A0 = P.conv_diff(2, side, 20.0, (1.0, 0.3))
+    n = A0.n
+    rng = np.random.default_rng(seed)
+    r = np.arange(0, n, 7)
+    S = A0.scipy() + sp.csr_matrix((-1e-3 * rng.uniform(0.5, 1.0, len(r)), (r, (r + n // 2) % n)), shape=(n, n))
+    S = S.tocsr()
+    S.sort_indices()
+    return P.CSR(n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data), S
+
+
 # ---------------------------------------------------------------------------
 # SpMV
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("case", ["cfg1", "ragged2d", "aniso3d", "varcoef27", "irregular", "longrow"])
+# layout the library picks: 2 = sliced copy with 16-bit column offsets, 1 = with
+# 32-bit columns, 0 = CSR row tiles only (a row longer than 512)
+SPMV_LAYOUT = {"cfg1": 2, "ragged2d": 2, "aniso3d": 2, "varcoef27": 2, "irregular": 0, "longrow": 0, "farcols": 1}
+
+
+@pytest.mark.parametrize("case", ["cfg1", "ragged2d", "aniso3d", "varcoef27", "irregular", "longrow", "farcols"])
 def test_spmv_parity(case):
     say("spmv", case)
     if case == "cfg1":
@@ -93,9 +114,12 @@ def test_spmv_parity(case):
         A = P.varcoef27(17, 3)
     elif case == "irregular":
         A = ragged_matrix_with_long_row()
+    elif case == "farcols":
+        A, _ = far_column_matrix()
     else:
         A = long_row_matrix()
     M = B.Matrix.from_csr(A)
+    assert M.layout == SPMV_LAYOUT[case]
     x = np.random.default_rng(1).uniform(-1, 1, A.n)
     for prec, dt in (("fp64", np.float64), ("fp32", np.float32)):
         xd = dev_tensor(x.astype(dt))
@@ -322,6 +346,27 @@ def test_row_tiled_path_solve():
     b = dev_tensor(bb)
     for inner in ("fp32", "fp64"):
         say("row-tiled solve", inner)
+        x, d, h = B.solve(M, b, restart=30, inner=inner, rtol=1e-10, check_mode=0, hist_cap=20000)
+        ref = (L.gmres(A, bb, m=30, rtol=1e-10, check_mode=0, max_iters=30) if inner == "fp64" else
+               L.gmres_ir(A, bb, m=30, rtol=1e-10, inner="fp32", check_mode=0, max_iters=30))
+        tol = 1e-10 if inner == "fp64" else HIST_TOL_FP32
+        assert np.max(np.abs(h[:30] - np.array(ref.hist[:30]))) <= tol
+        assert d["status"] == B.OK
+        assert np.linalg.norm(bb - S @ x.cpu().numpy()) / np.linalg.norm(bb) <= 1e-10
+
+
+def test_far_column_solve():
+    """Columns beyond the 16-bit offset range keep the sliced copy on 32-bit
+    columns; at 69696 rows the fused SpMV + projection runs its sliced kernel
+    on them.  First cycle against the oracle's, then the fp64 residual."""
+    A, S = far_column_matrix()
+    u = np.random.default_rng(12).uniform(-1, 1, A.n)
+    bb = S @ u
+    M = B.Matrix.from_csr(A)
+    assert M.layout == 1
+    b = dev_tensor(bb)
+    for inner in ("fp32", "fp64"):
+        say("far-column solve", inner)
         x, d, h = B.solve(M, b, restart=30, inner=inner, rtol=1e-10, check_mode=0, hist_cap=20000)
         ref = (L.gmres(A, bb, m=30, rtol=1e-10, check_mode=0, max_iters=30) if inner == "fp64" else
                L.gmres_ir(A, bb, m=30, rtol=1e-10, inner="fp32", check_mode=0, max_iters=30))
