@@ -560,10 +560,16 @@ struct Ctx {
     double b = spmv_bytes(sell_path) + sT() * n * 2 + sS() * n * nread + (SCALED ? sS() * n : 0.0);
     int g;
     if (sell_path) {
-      auto kern = k_spmv_proj_sell<T, S, SLOTS, SCALED>;
+      // up to 32 columns: eight waves per block with half the column slots
+      // each (same KMAX), twice the loads in flight per CU at the same number
+      // of partial sums (measured on the 1000^2 system: 18.8 -> 16.4 us at
+      // k <= 16, 27.2 -> 25.0 us at k <= 32; 37.2 -> 41.1 us at k <= 64, so
+      // wider bases keep four waves)
+      constexpr int NW = KMAX <= 32 ? 2 * NWAVES : NWAVES;
+      auto kern = k_spmv_proj_sell<T, S, KMAX / NW, SCALED, NW>;
       constexpr int SPS = (sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS) / SELL_C;  // slices per stage
-      g = std::max(1, std::min(resident_grid((const void*)kern, 0), (A->nslices + SPS - 1) / SPS));
-      prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(BLOCK), 0, stream, Ain, src, V, L.ldv, j, w1, st,
+      g = std::max(1, std::min(resident_grid((const void*)kern, 0, NW * WAVE), (A->nslices + SPS - 1) / SPS));
+      prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(NW * WAVE), 0, stream, Ain, src, V, L.ldv, j, w1, st,
                    part, (const T*)norm_part(), nB);
     } else {
       auto kern = k_spmv_proj<T, S, SLOTS, SCALED>;

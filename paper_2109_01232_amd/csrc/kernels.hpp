@@ -348,7 +348,7 @@ struct ProjGroup<bf16_t, float> {
   }
 };
 
-template <typename T, typename S, int SLOTS, bool SCALED>
+template <typename T, typename S, int SLOTS, bool SCALED, int NW = NWAVES>
 __device__ __forceinline__ void project_rows(const S* __restrict__ V, long ldv, int j, int C, int base, int nrows,
                                              const T* ys, const T* vs, T (&acc)[SLOTS], int lane, int wid) {
   constexpr int G = ProjGroup<S, T>::G;
@@ -362,7 +362,7 @@ __device__ __forceinline__ void project_rows(const S* __restrict__ V, long ldv, 
     for (int i = 0; i < G; ++i) yv[i] = (rb + i < nrows) ? ys[rb + i] : T(0);
 #pragma unroll
     for (int q = 0; q < SLOTS; ++q) {
-      const int c = wid + NWAVES * q;
+      const int c = wid + NW * q;
       if (c < C) {
         T vv[G];
         if (SCALED && c == j) {
@@ -474,17 +474,19 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict_
   store_partials(s_vals, C, part);
 }
 
-// The same over the sliced ELLPACK copy: a block takes a contiguous range of
-// stages of STAGE rows (16 slices in fp32, 8 in fp64); per stage each wave
-// sums its slices' rows (one row per lane), stores w and v_j and stages them
-// in LDS, then the block projects the stage's rows as above.
-template <typename T, typename S, int SLOTS, bool SCALED>
-__global__ __launch_bounds__(BLOCK) void k_spmv_proj_sell(Csr A, const T* __restrict__ src, S* __restrict__ V,
+// The same over the sliced ELLPACK copy: a block of NW waves takes a
+// contiguous range of stages of STAGE rows (16 slices in fp32, 8 in fp64); per
+// stage each wave sums its slices' rows (one row per lane), stores w and v_j
+// and stages them in LDS, then the block projects the stage's rows as above
+// (wave w: columns w, w + NW, ...).  Eight waves per block double the loads in
+// flight per CU at the same number of blocks, and so of partial sums.
+template <typename T, typename S, int SLOTS, bool SCALED, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_spmv_proj_sell(Csr A, const T* __restrict__ src, S* __restrict__ V,
                                                           long ldv, int j, T* __restrict__ w_out, State st,
                                                           T* __restrict__ part, const T* __restrict__ norm_part,
                                                           int nB) {
   const int flags = load_flags(st.hdr);  // tested after the prologue, as above
-  constexpr int KMAX = NWAVES * SLOTS;
+  constexpr int KMAX = NW * SLOTS;
   constexpr int STAGE = sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS;
   constexpr int SPS = STAGE / SELL_C;  // slices per stage
   __shared__ T ys[STAGE];
@@ -504,7 +506,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj_sell(Csr A, const T* __rest
   const int g0 = (int)((long)nstages * lb / B);
   const int g1 = (int)((long)nstages * (lb + 1) / B);
   for (int g = g0; g < g1; ++g) {
-    for (int i = wid; i < SPS; i += NWAVES) {
+    for (int i = wid; i < SPS; i += NW) {
       const int sl = g * SPS + i;
       const int r = sl * SELL_C + lane;
       T y = T(0), vj = T(0);
@@ -527,19 +529,19 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj_sell(Csr A, const T* __rest
     __syncthreads();
     const int base = g * STAGE;
     const int nrows = A.n - base < STAGE ? A.n - base : STAGE;
-    project_rows<T, S, SLOTS, SCALED>(V, ldv, j, C, base, nrows, ys, vs, acc, lane, wid);
+    project_rows<T, S, SLOTS, SCALED, NW>(V, ldv, j, C, base, nrows, ys, vs, acc, lane, wid);
     __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q) {
-    const int c = wid + NWAVES * q;
+    const int c = wid + NW * q;
     if (c < C) {
       const T v = wave_sum(acc[q]);
       if (lane == 0) s_vals[c] = v;
     }
   }
   __syncthreads();
-  store_partials(s_vals, C, part);
+  for (int c = threadIdx.x; c < C; c += NW * WAVE) part[(size_t)c * MAX_BLOCKS + blockIdx.x] = s_vals[c];
 }
 
 // h[c0 + c] = V[:, c0 + c]^T w for c < nc <= 64 (restart lengths beyond the
