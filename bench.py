@@ -121,8 +121,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU decomposition is a design in DESIGN.md, not built)",
+        print(json.dumps({"error": "this solver runs on one GPU only; --gpus must be 1 "
+                                   "(a row-block decomposition over several GPUs is designed, not built)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
