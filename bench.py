@@ -118,6 +118,9 @@ def main():
                     help="also time the other workloads (150^3 anisotropic + polynomial, 128^3 27-point "
                          "bf16/fp32/fp64, 64^2 parity system); one JSON line each, after the main line")
     ap.add_argument("--suite-only", action="store_true")
+    ap.add_argument("--suite-case", default=None,
+                    help="run only the suite solves whose 'name/inner/basis/restart/degree' label contains this "
+                         "text (e.g. 'aniso3d_150_7pt/fp32/fp32/100/0'); for profiling one workload")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -339,25 +342,29 @@ def suite(args):
 
     steps = max(1, min(args.steps, 3))
     ws = B.Workspace()
-    cases = []
-    s3 = P.aniso3d_system(0)
-    cases.append(("aniso3d_150_7pt", s3, [("fp64", "fp64", 100, 0), ("fp32", "fp32", 100, 0),
-                                          ("fp32", "fp32", 100, 10), ("fp32", "fp32", 100, 20),
-                                          ("fp32", "fp32", 100, 30), ("fp32", "fp32", 100, 40)]))
-    s4 = P.varcoef27_system(0)
-    cases.append(("varcoef27_128", s4, [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0), ("fp32", "bf16", 50, 0)]))
+    # systems are generated only for the cases that run
+    cases = [("aniso3d_150_7pt", lambda: P.aniso3d_system(0),
+              [("fp64", "fp64", 100, 0), ("fp32", "fp32", 100, 0), ("fp32", "fp32", 100, 10),
+               ("fp32", "fp32", 100, 20), ("fp32", "fp32", 100, 30), ("fp32", "fp32", 100, 40)]),
+             ("varcoef27_128", lambda: P.varcoef27_system(0),
+              [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0), ("fp32", "bf16", 50, 0)])]
     for seed in range(1, 5):
         # the headline workload at its other seeds (Peclet number drawn per seed)
-        s2 = P.convdiff2d_system(seed)
-        cases.append((f"convdiff2d_1000_seed{seed}", s2, [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0)]))
-    s1 = P.parity_system()
-    cases.append(("convdiff2d_64_parity", s1, [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0),
-                                               ("fp32", "bf16", 50, 0)]))
-    for name, sysm, cfgs in cases:
+        cases.append((f"convdiff2d_1000_seed{seed}", lambda seed=seed: P.convdiff2d_system(seed),
+                      [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0)]))
+    cases.append(("convdiff2d_64_parity", P.parity_system,
+                  [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0), ("fp32", "bf16", 50, 0)]))
+    for name, make_system, cfgs in cases:
+        if args.suite_case and not any(args.suite_case in f"{name}/{i}/{b}/{m}/{d}" for i, b, m, d in cfgs):
+            continue
         log("suite", name)
+        sysm = make_system()
         M = B.Matrix.from_csr(sysm.A)
         b = torch.from_numpy(sysm.b).cuda()
         for inner, basis, m, deg in cfgs:
+            label = f"{name}/{inner}/{basis}/{m}/{deg}"
+            if args.suite_case and args.suite_case not in label:
+                continue
             roots, t_setup = None, 0.0
             if deg > 0:
                 torch.cuda.synchronize()
@@ -375,7 +382,7 @@ def suite(args):
             _, dp, _ = B.gmresir_solve(M, b, x, prof, poly_roots=roots, ws=ws)
             gbps = {c: (dp["cat_bytes"][c] / dp["cat_time_s"][c] / 1e9) for c in B.CATEGORIES
                     if dp["cat_time_s"][c] > 0}
-            rec = {"suite": name, "N": sysm.A.n, "nnz": sysm.A.nnz, "meta": {k: v for k, v in sysm.meta.items()
+            rec = {"suite": name, "case": label, "N": sysm.A.n, "nnz": sysm.A.nnz, "meta": {k: v for k, v in sysm.meta.items()
                                                                               if isinstance(v, (int, float, str))},
                    "inner": inner, "basis": basis, "restart": m,
                    "poly_degree": deg, "status": st, "time_to_1e-10_s": t, "poly_setup_s": t_setup,
