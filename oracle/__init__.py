@@ -19,8 +19,8 @@ variant rounds each basis vector to bfloat16.
 
 Modules
 -------
-``linalg``    SpMV, bf16 rounding, the GMRES cycle (CGS2 + Givens), GMRES(m)
-              and GMRES-IR.
+``linalg``    SpMV, bf16 rounding, the GMRES cycle (CGS2 + Givens), GMRES(m),
+              GMRES-IR and GMRES-FD (Section "Mixed Precision GMRES-FD").
 ``poly``      GMRES-polynomial preconditioner: harmonic Ritz values, Leja
               ordering, product-form application, dense evaluation.
 ``features``  the 16 matrix/residual features of the parameter chooser.

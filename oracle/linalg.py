@@ -265,7 +265,7 @@ def gmres(A, b, x0=None, m=50, rtol=1e-10, max_iters=100000, check_mode=0, keep_
 
 
 def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
-             max_iters=100000, check_mode=0, poly_roots=None, keep_iterates=False):
+             max_iters=100000, check_mode=0, poly_roots=None, keep_iterates=False, max_refinements=0):
     """GMRES-IR (Algorithm 2): fp64 residual and update around an inner GMRES(m).
 
     ``inner`` is ``"fp32"`` or ``"fp64"``; ``basis`` is ``"same"`` or ``"bf16"``
@@ -274,7 +274,8 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
     restarts in its own precision from ``rhat - A_in u``.  ``poly_roots``
     (ordered, see ``oracle.poly``) turns on right preconditioning by
     ``M = p(A_in)``: the inner operator is ``A_in p(A_in)`` and the correction is
-    ``p(A_in) V y``; residuals are those of ``A``.
+    ``p(A_in) V y``; residuals are those of ``A``.  ``max_refinements > 0``
+    stops (``NOT_CONVERGED``) after that many refinements.
     """
     wp = np.float32 if inner == "fp32" else np.float64
     if basis == "bf16" and wp != np.float32:
@@ -309,7 +310,7 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
             break
         if rel <= rtol:
             break
-        if res.iters >= max_iters:
+        if res.iters >= max_iters or (max_refinements > 0 and res.refinements >= max_refinements):
             res.status = NOT_CONVERGED
             break
         rhat = (r / gamma).astype(wp)
@@ -353,6 +354,48 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
     res.x = x
     res.rel_resid = float(norm2(b - spmv(M64, x)) / beta)
     return res
+
+
+def gmres_fd(A, b, switch, m=50, rtol=1e-10, max_iters=100000, check_mode=0, basis="same"):
+    """GMRES-FD (Section "Mixed Precision GMRES-FD"): GMRES(m) in single
+    precision for ``switch`` iterations, then GMRES(m) in double precision
+    with the single-precision solution as its initial vector.
+
+    The single-precision phase is written as one refinement of ``gmres_ir``
+    with an fp32 inner solve of ``switch`` iterations restarted in fp32: that
+    is fp32 GMRES(m) on the system scaled by ``1 / ||b||`` (a scaling that
+    changes nothing in exact arithmetic; in fp32 it keeps the right-hand side
+    in range), whose solution is scaled back in fp64.  Its implicit early
+    exit is off, so the phase runs its full length; if the explicit fp64
+    residual at the switch already meets ``rtol`` the double phase is skipped.
+    Returns a ``Result`` whose counters cover both phases and whose ``xs``
+    holds the iterate at the switch.
+    """
+    x = np.zeros(A.n)
+    total = Result(x, NOT_CONVERGED, 0, 0, 0.0, [], [], [], [])
+    if switch > 0:
+        single = gmres_ir(A, b, m=m, rtol=rtol, inner="fp32", basis=basis, cap=switch,
+                          max_iters=min(switch, max_iters), check_mode=0, max_refinements=1)
+        total.status, total.iters, total.refinements = single.status, single.iters, single.refinements
+        total.hist.extend(single.hist)
+        total.cycle_starts.extend(single.cycle_starts)
+        total.outer.extend(single.outer)
+        total.xs.append(single.x.copy())
+        x = single.x
+    if total.status == NOT_CONVERGED and total.iters < max_iters:
+        double = gmres(A, b, x0=x, m=m, rtol=rtol, max_iters=max_iters - total.iters, check_mode=check_mode)
+        offset = len(total.hist)
+        total.status = double.status
+        total.iters += double.iters
+        total.refinements += double.refinements
+        total.hist.extend(double.hist)
+        total.cycle_starts.extend(c + offset for c in double.cycle_starts)
+        total.outer.extend(double.outer)
+        x = double.x
+    total.x = x
+    total.rel_resid = float(norm2(np.asarray(b, dtype=np.float64) - spmv(csr_matrix(A, np.float64), x))
+                            / max(float(norm2(np.asarray(b, dtype=np.float64))), np.finfo(float).tiny))
+    return total
 
 
 def gmres_single(A, b, m=50, rtol=1e-10, max_iters=5000):
