@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-parameter variant")
+    ap.add_argument("--no-fd", action="store_true", help="skip the GMRES-FD switch-point sweep")
+    ap.add_argument("--fd-switch", default="500,1000,2000",
+                    help="GMRES-FD switch points (fp32 iterations before fp64 GMRES takes over)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--max-iters", type=int, default=1_000_000,
                     help="cap on inner iterations of the timed solves (short hardware-counter runs only)")
@@ -261,6 +264,32 @@ def main():
         out["speedup_vs_fp64"] = t_64 / t_ir
         if "learned" in out:
             out["learned"]["speedup_vs_fp64"] = t_64 / out["learned"]["s"]
+        for f in out.get("gmres_fd", {}).get("switch_points", []):
+            f["speedup_vs_fp64"] = t_64 / f["s"]
+
+    if not args.no_fd:
+        # GMRES-FD: fp32 GMRES(m) up to the switch point, then fp64 GMRES(m)
+        # from its solution; the paper sweeps the switch point
+        fd = []
+        for sw in [int(v) for v in args.fd_switch.split(",") if v]:
+            p_fd = B.make_params(restart=args.restart, inner="fp32", basis=args.basis, rtol=1e-10, check_mode=1)
+            x.zero_()
+            B.gmresir_solve_fd(M, b, x, p_fd, sw, ws=ws)
+            torch.cuda.synchronize()
+            reps = max(1, min(args.steps, 2))
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                x.zero_()
+                st_f, d_f, _ = B.gmresir_solve_fd(M, b, x, p_fd, sw, ws=ws)
+            torch.cuda.synchronize()
+            t_f = (time.perf_counter() - t0) / reps
+            xs_f = x.cpu().numpy()
+            true_f = float(np.linalg.norm(system.b - A.scipy() @ xs_f) / np.linalg.norm(system.b))
+            log(f"FD switch {sw}: {t_f:.4f} s/solve iters={d_f['iters']} resid={true_f:.3e}")
+            fd.append({"switch": sw, "s": t_f, "iters": d_f["iters"], "status": B.status_string(st_f),
+                       "rel_resid_true": true_f})
+        out["gmres_fd"] = {"switch_points": fd,
+                           "what": "fp32 GMRES(m) for `switch` iterations, then fp64 GMRES(m) from its solution"}
 
     if not args.no_profile:
         # one more solve with HIP events around every kernel (on the solve's stream)

@@ -162,6 +162,33 @@ int gmresir_solve(const gmresir_matrix* A, const double* b, double* x, const gmr
                   const double* poly_roots_host, void* ws, size_t ws_bytes, gmresir_result* res_host,
                   double* hist_host, int64_t hist_cap, void* stream);
 
+/* ---- GMRES-FD (Section "Mixed Precision GMRES-FD") ---------------------- */
+
+/* Workspace bytes of gmresir_solve_fd (0 if the arguments are invalid). */
+size_t gmresir_fd_workspace_bytes(const gmresir_matrix* A, const gmresir_params* p, int64_t switch_iters);
+
+/* GMRES-FD, the paper's float-to-double variant: restarted GMRES(m) run
+   entirely in fp32 for switch_iters inner iterations, then fp64 GMRES(m)
+   started from the fp32 solution, until the relative residual reaches rtol.
+   The fp32 phase solves the system scaled by 1 / ||b|| (b / ||b|| rounded to
+   fp32, x0 = 0 after the scaling; its restarts use the fp32 residual of the
+   fp32 matrix copy) and its solution is scaled back and added to x in fp64;
+   the explicit fp64 residual is evaluated once, at the switch (if it already
+   meets rtol, the fp64 phase is skipped).  switch_iters = 0 is plain fp64
+   GMRES(m).
+   Parameters: restart, max_iters (the total over both phases), rtol and
+   profile as for gmresir_solve; inner_prec must be FP32 and basis_prec FP32
+   or BF16 (the fp32 phase's basis); inner_cap and poly_degree must be 0;
+   check_mode applies to the fp64 phase only (the fp32 phase runs its full
+   length).  b, x, ws, res_host, hist_host as for gmresir_solve (ws:
+   gmresir_fd_workspace_bytes bytes); hist_host receives the fp32 phase's
+   per-iteration values, then the fp64 phase's.  res_host->iters counts both
+   phases; the status is that of the last phase run.  Errors: INVALID_ARG
+   (as above, switch_iters < 0 or >= 2^31), WORKSPACE, HIP, NUMERIC. */
+int gmresir_solve_fd(const gmresir_matrix* A, const double* b, double* x, const gmresir_params* p,
+                     int64_t switch_iters, void* ws, size_t ws_bytes, gmresir_result* res_host,
+                     double* hist_host, int64_t hist_cap, void* stream);
+
 /* ---- polynomial preconditioner (Section "Preconditioning") -------------- */
 
 /* Workspace bytes for gmresir_poly_setup / gmresir_poly_apply of degree <= max_degree. */

@@ -87,6 +87,9 @@ _SIGS = {
     "gmresir_workspace_bytes": (_sz, [_vp, ctypes.POINTER(Params)]),
     "gmresir_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(Params), _dp, _vp, _sz,
                                      ctypes.POINTER(Result), _dp, _i64, _vp]),
+    "gmresir_fd_workspace_bytes": (_sz, [_vp, ctypes.POINTER(Params), _i64]),
+    "gmresir_solve_fd": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(Params), _i64, _vp, _sz,
+                                        ctypes.POINTER(Result), _dp, _i64, _vp]),
     "gmresir_poly_workspace_bytes": (_sz, [_vp, _i32]),
     "gmresir_poly_setup": (ctypes.c_int, [_vp, _i32, _vp, ctypes.c_uint64, _vp, _sz, _dp, _dp, _vp]),
     "gmresir_poly_apply": (ctypes.c_int, [_vp, _i32, _dp, _vp, _vp, _vp, _sz, _vp]),
@@ -316,6 +319,39 @@ def solve(A: Matrix, b, x0=None, ws=None, hist_cap=0, poly_roots=None, **kw):
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     p = make_params(**kw)
     st, d, h = gmresir_solve(A, b, x, p, poly_roots=poly_roots, ws=ws, hist_cap=hist_cap)
+    return x, d, h
+
+
+def gmresir_fd_workspace_bytes(A: Matrix, p: Params, switch_iters: int) -> int:
+    return int(lib().gmresir_fd_workspace_bytes(A.handle, ctypes.byref(p), switch_iters))
+
+
+def gmresir_solve_fd(A: Matrix, b, x, p: Params, switch_iters: int, ws=None, hist_cap=0):
+    """Run gmresir_solve_fd (GMRES-FD); x (fp64 device tensor) is updated in place.
+
+    Returns (status, result dict, history numpy array).
+    """
+    need = gmresir_fd_workspace_bytes(A, p, switch_iters)
+    if need == 0:
+        raise GmresirError("gmresir_fd_workspace_bytes", ERR_INVALID_ARG)
+    buf = (ws or Workspace(A.device)).get(need)
+    res = Result()
+    hist = np.zeros(max(hist_cap, 0))
+    st = lib().gmresir_solve_fd(A.handle, _ptr(b), _ptr(x), ctypes.byref(p), switch_iters, _ptr(buf), buf.numel(),
+                                ctypes.byref(res), hist.ctypes.data_as(_dp) if hist_cap > 0 else None, hist_cap,
+                                _stream())
+    if st < 0:
+        raise GmresirError("gmresir_solve_fd", st)
+    d = res.as_dict()
+    return st, d, hist[: min(hist_cap, d["iters"])]
+
+
+def solve_fd(A: Matrix, b, switch_iters: int, x0=None, ws=None, hist_cap=0, **kw):
+    """Convenience for GMRES-FD: returns (x, result dict, history)."""
+    torch = _torch()
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    p = make_params(inner="fp32", **kw)
+    st, d, h = gmresir_solve_fd(A, b, x, p, switch_iters, ws=ws, hist_cap=hist_cap)
     return x, d, h
 
 

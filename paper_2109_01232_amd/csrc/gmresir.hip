@@ -822,7 +822,7 @@ struct Ctx {
 template <typename T, typename S>
 int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresir_params* p,
                const double* roots, char* ws, const Layout& L, gmresir_result* res, double* hist, int64_t hist_cap,
-               hipStream_t stream) {
+               hipStream_t stream, int max_refinements = 0) {
   Prof prof;
   prof.on = p->profile == 1;
   prof.stream = stream;
@@ -873,7 +873,7 @@ int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresi
       break;
     }
     if (rel <= p->rtol) break;
-    if (res->iters >= p->max_iters) {
+    if (res->iters >= p->max_iters || (max_refinements > 0 && res->refinements >= max_refinements)) {
       status = GMRESIR_NOT_CONVERGED;
       break;
     }
@@ -1008,6 +1008,42 @@ bool ws_ok(const void* ws, size_t have, size_t need) {
   if (((uintptr_t)ws) % ALIGN) return set_error("workspace must be 256-byte aligned"), false;
   if (have < need) return set_error("workspace has %zu bytes, %zu needed", have, need), false;
   return true;
+}
+
+// GMRES-FD (Section "Mixed Precision GMRES-FD"): the two phases are ordinary
+// solves.  Phase one is one refinement whose inner solve is fp32 GMRES(m),
+// restarted in fp32 for `switch_iters` iterations (its right-hand side is
+// b / ||b|| rounded to fp32, its solution is scaled back by ||b|| in fp64);
+// phase two is fp64 GMRES(m) from that solution.
+bool fd_params(const gmresir_params* p, int64_t switch_iters, gmresir_params* q32, gmresir_params* q64,
+               const char** why) {
+  if (!valid_params(p, why)) return false;
+  if (p->inner_prec != GMRESIR_FP32) return *why = "GMRES-FD needs inner_prec FP32 (its first phase)", false;
+  if (p->inner_cap != 0) return *why = "GMRES-FD needs inner_cap 0 (the switch point sets phase one)", false;
+  if (p->poly_degree != 0) return *why = "GMRES-FD takes no polynomial preconditioner", false;
+  if (switch_iters < 0 || switch_iters > INT32_MAX) return *why = "switch_iters must be in [0, 2^31)", false;
+  *q32 = *p;
+  q32->inner_cap = (int32_t)std::max<int64_t>(switch_iters, 1);
+  q32->max_iters = std::max<int64_t>(std::min<int64_t>(switch_iters, p->max_iters), 1);
+  q32->check_mode = 0;  // phase one runs its full length
+  *q64 = *p;
+  q64->inner_prec = GMRESIR_FP64;
+  q64->basis_prec = GMRESIR_FP64;
+  return true;
+}
+
+void add_result(gmresir_result* acc, const gmresir_result& r) {
+  acc->status = r.status;
+  acc->refinements += r.refinements;
+  acc->iters += r.iters;
+  acc->cycles += r.cycles;
+  acc->rel_resid_true = r.rel_resid_true;
+  acc->rel_resid_implicit = r.rel_resid_implicit;
+  for (int i = 0; i < GMRESIR_NCAT; ++i) {
+    acc->cat_time_s[i] += r.cat_time_s[i];
+    acc->cat_bytes[i] += r.cat_bytes[i];
+    acc->cat_launches[i] += r.cat_launches[i];
+  }
 }
 
 }  // namespace
@@ -1241,6 +1277,63 @@ int gmresir_solve(const gmresir_matrix* A, const double* b, double* x, const gmr
     st = solve_impl<float, float>(A, b, x, p, poly_roots, (char*)ws, L, res, hist, hist_cap, s);
   else
     st = solve_impl<float, bf16_t>(A, b, x, p, poly_roots, (char*)ws, L, res, hist, hist_cap, s);
+  res->status = st;
+  res->solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+size_t gmresir_fd_workspace_bytes(const gmresir_matrix* A, const gmresir_params* p, int64_t switch_iters) {
+  const char* why = "";
+  gmresir_params q32, q64;
+  if (!A || !fd_params(p, switch_iters, &q32, &q64, &why)) return 0;
+  return std::max(make_layout(A->n, &q32).total, make_layout(A->n, &q64).total);
+}
+
+int gmresir_solve_fd(const gmresir_matrix* A, const double* b, double* x, const gmresir_params* p,
+                     int64_t switch_iters, void* ws, size_t ws_bytes, gmresir_result* res, double* hist,
+                     int64_t hist_cap, void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  const char* why = "";
+  gmresir_params q32, q64;
+  if (!A || !b || !x || !res) {
+    set_error("gmresir_solve_fd: NULL argument");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (!fd_params(p, switch_iters, &q32, &q64, &why)) {
+    set_error("gmresir_solve_fd: %s", why);
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (hist_cap < 0 || (hist_cap > 0 && !hist)) {
+    set_error("gmresir_solve_fd: bad history buffer");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  const size_t need = std::max(make_layout(A->n, &q32).total, make_layout(A->n, &q64).total);
+  if (!ws_ok(ws, ws_bytes, need)) return GMRESIR_ERR_WORKSPACE;
+  memset(res, 0, sizeof(*res));
+  hipStream_t s = (hipStream_t)stream;
+  int st = GMRESIR_NOT_CONVERGED;
+  int64_t hist_used = 0;
+  if (switch_iters > 0) {
+    gmresir_result r1{};
+    const Layout L1 = make_layout(A->n, &q32);
+    if (q32.basis_prec == GMRESIR_FP32)
+      st = solve_impl<float, float>(A, b, x, &q32, nullptr, (char*)ws, L1, &r1, hist, hist_cap, s, 1);
+    else
+      st = solve_impl<float, bf16_t>(A, b, x, &q32, nullptr, (char*)ws, L1, &r1, hist, hist_cap, s, 1);
+    r1.status = st;
+    add_result(res, r1);
+    hist_used = std::min<int64_t>(hist_cap, r1.iters);
+  }
+  // phase two unless phase one converged or failed
+  if (st == GMRESIR_NOT_CONVERGED && res->iters < p->max_iters) {
+    q64.max_iters = p->max_iters - res->iters;
+    gmresir_result r2{};
+    const Layout L2 = make_layout(A->n, &q64);
+    st = solve_impl<double, double>(A, b, x, &q64, nullptr, (char*)ws, L2, &r2, hist ? hist + hist_used : nullptr,
+                                    hist_cap - hist_used, s);
+    r2.status = st;
+    add_result(res, r2);
+  }
   res->status = st;
   res->solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return st;
