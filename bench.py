@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--no-fd", action="store_true", help="skip the GMRES-FD switch-point sweep")
     ap.add_argument("--fd-switch", default="500,1000,2000",
                     help="GMRES-FD switch points (fp32 iterations before fp64 GMRES takes over)")
+    ap.add_argument("--spmv-study", action="store_true",
+                    help="only time fp64 vs fp32 SpMV over the stencil families (1000 calls, min of 3), "
+                         "one JSON line per family")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--max-iters", type=int, default=1_000_000,
                     help="cap on inner iterations of the timed solves (short hardware-counter runs only)")
@@ -146,6 +149,10 @@ def main():
 
     if args.suite_only:
         suite(args)
+        return
+
+    if args.spmv_study:
+        spmv_study()
         return
 
     if args.copy_calibration:
@@ -342,6 +349,51 @@ def main():
     print(json.dumps(out), flush=True)
     if args.suite:
         suite(args)
+
+
+def spmv_study(calls=1000, reps=3):
+    """fp64 vs fp32 SpMV time over constant-coefficient stencil families
+    (2D on 1500^2, 3D on 130^3 grids), beside the paper's cache model
+    5w / (2w + 1) (perfect reuse of x in fp32, none in fp64)."""
+    import numpy as np
+    import torch
+
+    from paper_2109_01232_amd import binding as B
+    from paper_2109_01232_amd import problems as P
+
+    for name in P.STENCILS:
+        dim = P.STENCILS[name][0]
+        n = 1500 if dim == 2 else 130
+        A = P.stencil_matrix(name, n)
+        M = B.Matrix.from_csr(A)
+        x = np.random.default_rng(0).uniform(-1, 1, A.n)
+        rec = {"metric": "spmv_study", "stencil": name, "N": A.n, "nnz": A.nnz,
+               "nnz_per_row": A.nnz / A.n, "max_row_nnz": int(np.diff(A.rowptr).max()), "layout": M.layout}
+        for prec, dt, sv in (("fp64", torch.float64, 8), ("fp32", torch.float32, 4)):
+            xd = torch.from_numpy(x).to(dt).cuda()
+            yd = torch.empty_like(xd)
+            for _ in range(10):
+                B.gmresir_spmv(M, xd, yd, prec)
+            best = float("inf")
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(calls):
+                    B.gmresir_spmv(M, xd, yd, prec)
+                e1.record()
+                torch.cuda.synchronize()
+                best = min(best, e0.elapsed_time(e1) * 1e3 / calls)
+            alg = (sv + 4) * A.nnz + 4 * (A.n + 1) + 2 * sv * A.n
+            rec[prec + "_us"] = best
+            rec[prec + "_GBps_csr_bytes"] = alg / (best * 1e-6) / 1e9
+        w = A.nnz / A.n
+        rec["speedup_fp32"] = rec["fp64_us"] / rec["fp32_us"]
+        rec["model_speedup"] = 5 * w / (2 * w + 1)
+        log(f"spmv {name}: fp64 {rec['fp64_us']:.1f} us, fp32 {rec['fp32_us']:.1f} us, "
+            f"x{rec['speedup_fp32']:.2f} (model {rec['model_speedup']:.2f})")
+        print(json.dumps(rec), flush=True)
+        M.close()
+        del M
 
 
 def time_solves(M, b, p, roots, ws, steps):

@@ -99,3 +99,48 @@ def test_rhs_is_A_u():
     assert np.allclose(s.A.scipy() @ np.ones(s.A.n), s.b)
     # b = A * ones is nonzero only next to the boundary (interior rows sum to 0 when Pe terms cancel)
     assert s.A.n == 4096 and s.A.nnz == 20224
+
+
+# ---------------------------------------------------------------------------
+# constant-coefficient stencil families of the SpMV study
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", sorted(P.STENCILS))
+@pytest.mark.parametrize("n", [7, 16])
+def test_stencil_family_nnz_and_layout(name, n):
+    A = P.stencil_matrix(name, n)
+    assert A.nnz == P.stencil_nnz(name, n)
+    dim, pat = P.STENCILS[name]
+    assert A.n == n ** dim
+    counts = np.diff(A.rowptr)
+    assert counts.max() == len(pat)  # interior rows hold the whole stencil
+    for r in range(A.n):
+        c = A.colidx[A.rowptr[r]:A.rowptr[r + 1]]
+        assert np.all(np.diff(c) > 0) and c.min() >= 0 and c.max() < A.n
+
+
+def _tri(n, lo, mid, hi):
+    import scipy.sparse as sp
+
+    return sp.diags([np.full(n - 1, lo), np.full(n, mid), np.full(n - 1, hi)], [-1, 0, 1])
+
+
+@pytest.mark.parametrize("n", [5, 11])
+def test_stencil_families_equal_kronecker_forms(n):
+    import scipy.sparse as sp
+
+    I = sp.identity(n)
+    T = _tri(n, -1.0, 2.0, -1.0)
+    J = _tri(n, 1.0, 1.0, 1.0)
+    T4 = sp.diags([np.full(n - 2, 1.0), np.full(n - 1, -16.0), np.full(n, 30.0), np.full(n - 1, -16.0),
+                   np.full(n - 2, 1.0)], [-2, -1, 0, 1, 2])
+    forms = {
+        "laplace2d_5": sp.kron(I, T) + sp.kron(T, I),
+        "fourth2d_9": sp.kron(I, T4) + sp.kron(T4, I),
+        "box2d_9": 9.0 * sp.identity(n * n) - sp.kron(J, J),
+        "laplace3d_7": sp.kron(I, sp.kron(I, T)) + sp.kron(I, sp.kron(T, I)) + sp.kron(T, sp.kron(I, I)),
+        "box3d_27": 27.0 * sp.identity(n ** 3) - sp.kron(J, sp.kron(J, J)),
+    }
+    for name, K in forms.items():
+        A = P.stencil_matrix(name, n).scipy()
+        assert abs(A - K).max() == 0.0, name
