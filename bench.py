@@ -426,7 +426,11 @@ def suite(args):
     # systems are generated only for the cases that run
     cases = [("aniso3d_150_7pt", lambda: P.aniso3d_system(0),
               [("fp64", "fp64", 100, 0), ("fp32", "fp32", 100, 0), ("fp32", "fp32", 100, 10),
-               ("fp32", "fp32", 100, 20), ("fp32", "fp32", 100, 30), ("fp32", "fp32", 100, 40)]),
+               ("fp32", "fp32", 100, 20), ("fp32", "fp32", 100, 30), ("fp32", "fp32", 100, 40),
+               # fp64 GMRES(100) with the polynomial in fp64, and in fp32 ("fp64p32": an fp32 p(A)
+               # applied to fp64 vectors, everything else fp64)
+               ("fp64", "fp64", 100, 10), ("fp64p32", "fp64", 100, 10),
+               ("fp64", "fp64", 100, 40), ("fp64p32", "fp64", 100, 40)]),
              ("varcoef27_128", lambda: P.varcoef27_system(0),
               [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0), ("fp32", "bf16", 50, 0)])]
     for seed in range(1, 5):
@@ -453,12 +457,15 @@ def suite(args):
                 roots = B.gmresir_poly_setup(M, deg, seed=12345, ws=ws)
                 torch.cuda.synchronize()
                 t_setup = time.perf_counter() - t0
-            p = B.make_params(restart=m, inner=inner, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg)
+            pprec = "fp32" if inner == "fp64p32" else None
+            inner_p = "fp64" if inner == "fp64p32" else inner
+            p = B.make_params(restart=m, inner=inner_p, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg,
+                              poly_prec=pprec)
             t, st, d, x = time_solves(M, b, p, roots, ws, steps)
             xs = x.cpu().numpy()
             true = float(np.linalg.norm(sysm.b - sysm.A.scipy() @ xs) / np.linalg.norm(sysm.b))
-            prof = B.make_params(restart=m, inner=inner, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg,
-                                 profile=1)
+            prof = B.make_params(restart=m, inner=inner_p, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg,
+                                 profile=1, poly_prec=pprec)
             x.zero_()
             _, dp, _ = B.gmresir_solve(M, b, x, prof, poly_roots=roots, ws=ws)
             gbps = {c: (dp["cat_bytes"][c] / dp["cat_time_s"][c] / 1e9) for c in B.CATEGORIES

@@ -87,7 +87,11 @@ typedef struct {
                           1: also stop a cycle once the implicit residual reaches rtol,
                           then verify with the explicit fp64 residual */
   int32_t profile;     /* 1: time every kernel with HIP events (slower; fills cat_*) */
-  int32_t reserved;    /* must be 0 */
+  int32_t poly_prec;   /* precision of the polynomial p(A) (poly_degree > 0): 0 = that of the inner
+                          solve; GMRESIR_FP32 with inner_prec FP64 = an fp32 p(A) inside fp64 GMRES(m)
+                          (Section "Preconditioning", the case of an fp32 M applied to fp64 vectors:
+                          each application casts its fp64 input to fp32, runs the d fp32 SpMV steps on
+                          the fp32 copy of A and widens the result; every other operation stays fp64) */
 } gmresir_params;
 
 typedef struct {

@@ -265,7 +265,8 @@ def gmres(A, b, x0=None, m=50, rtol=1e-10, max_iters=100000, check_mode=0, keep_
 
 
 def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
-             max_iters=100000, check_mode=0, poly_roots=None, keep_iterates=False, max_refinements=0):
+             max_iters=100000, check_mode=0, poly_roots=None, keep_iterates=False, max_refinements=0,
+             poly_prec=None):
     """GMRES-IR (Algorithm 2): fp64 residual and update around an inner GMRES(m).
 
     ``inner`` is ``"fp32"`` or ``"fp64"``; ``basis`` is ``"same"`` or ``"bf16"``
@@ -275,7 +276,11 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
     (ordered, see ``oracle.poly``) turns on right preconditioning by
     ``M = p(A_in)``: the inner operator is ``A_in p(A_in)`` and the correction is
     ``p(A_in) V y``; residuals are those of ``A``.  ``max_refinements > 0``
-    stops (``NOT_CONVERGED``) after that many refinements.
+    stops (``NOT_CONVERGED``) after that many refinements.  ``poly_prec="fp32"``
+    with an fp64 inner solve applies the polynomial in single precision
+    (Section "Preconditioning": each application of an fp32 ``M`` to an fp64
+    vector casts it to fp32, multiplies by ``M`` with the fp32 matrix and
+    casts the result back); every other operation stays in fp64.
     """
     wp = np.float32 if inner == "fp32" else np.float64
     if basis == "bf16" and wp != np.float32:
@@ -294,7 +299,12 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
     if poly_roots is not None and len(poly_roots) > 1:
         from .poly import apply_product_form
 
-        papply = lambda v: apply_product_form(Min, poly_roots, v, wp)
+        if poly_prec == "fp32" and wp == np.float64:
+            M32 = csr_matrix(A, np.float32)
+            papply = lambda v: apply_product_form(M32, poly_roots, v.astype(np.float32),
+                                                  np.float32).astype(np.float64)
+        else:
+            papply = lambda v: apply_product_form(Min, poly_roots, v, wp)
     else:
         papply = None
     op = (lambda v: spmv(Min, papply(v))) if papply else (lambda v: spmv(Min, v))

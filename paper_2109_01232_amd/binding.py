@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
         ("poly_degree", ctypes.c_int32),
         ("check_mode", ctypes.c_int32),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("poly_prec", ctypes.c_int32),
     ]
 
 
@@ -252,7 +252,7 @@ class Matrix:
 
 
 def make_params(restart=50, inner="fp32", basis=None, rtol=1e-10, max_iters=1_000_000, inner_cap=0,
-                poly_degree=0, check_mode=1, profile=0) -> Params:
+                poly_degree=0, check_mode=1, profile=0, poly_prec=None) -> Params:
     if basis is None:
         basis = "fp64" if inner == "fp64" else "fp32"
     p = Params()
@@ -265,7 +265,7 @@ def make_params(restart=50, inner="fp32", basis=None, rtol=1e-10, max_iters=1_00
     p.poly_degree = poly_degree
     p.check_mode = check_mode
     p.profile = profile
-    p.reserved = 0
+    p.poly_prec = 0 if poly_prec is None else PREC[poly_prec]
     return p
 
 

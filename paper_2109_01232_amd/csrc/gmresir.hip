@@ -173,7 +173,7 @@ bool valid_params(const gmresir_params* p, const char** why) {
   if (p->poly_degree < 0 || p->poly_degree > 255) return *why = "poly_degree must be in [0, 255]", false;
   if (p->check_mode != 0 && p->check_mode != 1) return *why = "check_mode must be 0 or 1", false;
   if (p->profile != 0 && p->profile != 1) return *why = "profile must be 0 or 1", false;
-  if (p->reserved != 0) return *why = "reserved must be 0", false;
+  if (p->poly_prec != 0 && p->poly_prec != GMRESIR_FP32) return *why = "poly_prec must be 0 or FP32", false;
   return true;
 }
 
@@ -459,6 +459,11 @@ struct Ctx {
   Prof* prof;
   std::vector<PStep> prog;
   bool poly_on = false;  // inner operator is A p(A)
+  // fp32 polynomial inside an fp64 inner solve: its buffers are carved from
+  // the fp64 polynomial buffers (ldv fp32 entries each; two per buffer)
+  bool poly32 = false;
+  Csr A32;
+  float *q32[3] = {nullptr, nullptr, nullptr}, *s32 = nullptr, *y32 = nullptr;
 
 
   Ctx(const gmresir_matrix* A_, char* ws_, const Layout& L_, hipStream_t s, Prof* pr) : A(A_), stream(s), L(L_), ws(ws_), prof(pr) {
@@ -479,6 +484,14 @@ struct Ctx {
     n = (int)A->n;
     Ain = csr_of(A, sizeof(T) == 8);
     A64 = csr_of(A, true);
+    A32 = csr_of(A, false);
+    if (L.poly && sizeof(T) == 8) {
+      q32[0] = (float*)p0;
+      q32[1] = (float*)p1;
+      q32[2] = (float*)p2;
+      s32 = (float*)p0 + L.ldv;
+      y32 = (float*)p1 + L.ldv;
+    }
   }
 
   // LDS of the tiled SpMV products (none for the sliced ELLPACK kernels)
@@ -539,6 +552,58 @@ struct Ctx {
         prof->launch(cat, b, kern, dim3(g), dim3(BLOCK), lds_in(), stream, Ain, X, V, L.ldv, j, 0, W, w_scaled, y_out, D, cf, st, check_done, (const T*)norm_part(), nB);
       }
     }
+  }
+
+  // y_out = p(A) src with the fp32 copy of A and fp32 vectors (poly32); the
+  // same product-form program as run_poly, never scaled.
+  void run_poly32(float* src, float* y_out, int check_done, int cat) {
+    auto pick = [&](int b) -> float* {
+      switch (b) {
+        case PB_SRC: return src;
+        case PB_P0: return q32[0];
+        case PB_P1: return q32[1];
+        case PB_P2: return q32[2];
+        default: return nullptr;
+      }
+    };
+    const size_t lds = A->sell ? 0 : (size_t)A->lds_nnz * sizeof(float);
+    const double idx = (A->sell && A->sell_d16) ? 2.0 : 4.0;
+    for (size_t s = 0; s < prog.size(); ++s) {
+      const PStep& ps = prog[s];
+      PolyCoef<float> cf;
+      cf.ay = (float)ps.ay;
+      cf.aw = (float)ps.aw;
+      cf.ax = (float)ps.ax;
+      cf.at = (float)ps.at;
+      cf.bw = (float)ps.bw;
+      cf.bx = (float)ps.bx;
+      cf.bt = (float)ps.bt;
+      cf.has_y = ps.has_y;
+      cf.y_read = ps.y_read;
+      cf.has_d = ps.d != PB_NONE;
+      cf.has_w = ps.w != PB_NONE;
+      float* X = pick(ps.x);
+      float* W = pick(ps.w);
+      float* D = pick(ps.d);
+      double b = (4.0 + idx) * A->nnz + 4.0 * (A->n + 1) +
+                 4.0 * n * (1 + (ps.has_y ? 1 : 0) + (ps.y_read ? 1 : 0) + (cf.has_w ? 1 : 0) + (cf.has_d ? 1 : 0));
+      auto kern = k_poly_step<float, float, false>;
+      int g = grid_spmv(A);
+      prof->launch(cat, b, kern, dim3(g), dim3(BLOCK), lds, stream, A32, (const float*)X, (float*)nullptr, L.ldv, 0, 0,
+                   (const float*)W, 0, y_out, D, cf, st, check_done, (const float*)nullptr, 0);
+    }
+  }
+
+  void narrow(const double* x64, float* y, int check_done, int cat) {
+    auto kern = k_narrow;
+    int g = grid_rows((const void*)kern, n);
+    prof->launch(cat, 12.0 * n, kern, dim3(g), dim3(BLOCK), 0, stream, n, x64, y, st, check_done);
+  }
+
+  void widen(const float* x, double* y64, int check_done, int cat) {
+    auto kern = k_widen;
+    int g = grid_rows((const void*)kern, n);
+    prof->launch(cat, 12.0 * n, kern, dim3(g), dim3(BLOCK), 0, stream, n, x, y64, st, check_done);
   }
 
   // partials of ||w''||^2 written by k_update_norm (their own column, so
@@ -661,7 +726,15 @@ struct Ctx {
     const int nB = j > 0 ? norm_grid() : 0;
     prof->tag = j;
     prof->early = true;
-    if (poly_on) {
+    if (poly_on && poly32) {
+      auto kern = k_scale_narrow<T, S>;
+      int g = grid_rows((const void*)kern, n);
+      prof->launch(GMRESIR_CAT_POLY, sT() * n + sS() * n + 4.0 * n, kern, dim3(g), dim3(BLOCK), 0, stream, n,
+                   (const T*)wtmp, V, L.ldv, j, s32, st, (const T*)norm_part(), nB);
+      run_poly32(s32, y32, 1, GMRESIR_CAT_POLY);
+      widen(y32, (double*)z, 1, GMRESIR_CAT_POLY);
+      spmv_proj_dispatch<false>(z, j, kmax, nB);
+    } else if (poly_on) {
       run_poly(wtmp, true, j, z, 1, GMRESIR_CAT_POLY, nB);
       spmv_proj_dispatch<false>(z, j, kmax, nB);
     } else {
@@ -835,6 +908,7 @@ int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresi
       return GMRESIR_ERR_INVALID_ARG;
     }
     c.poly_on = true;
+    c.poly32 = sizeof(T) == 8 && p->poly_prec == GMRESIR_FP32;
   }
   const int m = p->restart;
   const int cap = p->inner_cap == 0 ? m : p->inner_cap;
@@ -890,7 +964,12 @@ int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresi
       } else {
         c.vy(c.z, kmax);
         T* upart = c.z;
-        if (L.poly) {
+        if (L.poly && c.poly32) {
+          c.narrow((const double*)c.z, c.s32, 0, GMRESIR_CAT_REFINE);
+          c.run_poly32(c.s32, c.y32, 0, GMRESIR_CAT_REFINE);
+          c.widen(c.y32, (double*)c.py, 0, GMRESIR_CAT_REFINE);
+          upart = c.py;
+        } else if (L.poly) {
           c.run_poly(c.z, false, 0, c.py, 0, GMRESIR_CAT_REFINE);
           upart = c.py;
         }

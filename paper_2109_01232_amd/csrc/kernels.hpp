@@ -1204,6 +1204,44 @@ __global__ __launch_bounds__(BLOCK) void k_axpy_x(int n, const T* __restrict__ u
   for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) x[r] = x[r] + gamma * (double)u[r];
 }
 
+// fp64 inner solve with an fp32 polynomial preconditioner (an fp32 M applied
+// to fp64 vectors: cast in, multiply in fp32, cast back).  Step one of an
+// iteration: v_j = wtmp / ||wtmp|| is stored as basis column j (fp64) and
+// rounded to fp32 as the polynomial's input.
+template <typename T, typename S>
+__global__ __launch_bounds__(BLOCK) void k_scale_narrow(int n, const T* __restrict__ wtmp, S* __restrict__ V, long ldv,
+                                                        int j, float* __restrict__ v32, State st,
+                                                        const T* __restrict__ norm_part, int nB) {
+  const int flags = load_flags(st.hdr);
+  const T inv = prev_inv_norm<T>(st, norm_part, nB);
+  if (flags & F_DONE) return;
+  int r0, r1;
+  block_rows(n, r0, r1);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
+    const T v = Basis<S, T>::round(wtmp[r] * inv);
+    Basis<S, T>::store(V + (size_t)j * ldv + r, v);
+    v32[r] = (float)v;
+  }
+}
+
+// y = fp32(x) (round to nearest even); check_done: no-op once the cycle stopped.
+__global__ __launch_bounds__(BLOCK) void k_narrow(int n, const double* __restrict__ x, float* __restrict__ y, State st,
+                                                  int check_done) {
+  if (check_done && (load_flags(st.hdr) & F_DONE)) return;
+  int r0, r1;
+  block_rows(n, r0, r1);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) y[r] = (float)x[r];
+}
+
+// y = fp64(x) (exact); check_done as above.
+__global__ __launch_bounds__(BLOCK) void k_widen(int n, const float* __restrict__ x, double* __restrict__ y, State st,
+                                                 int check_done) {
+  if (check_done && (load_flags(st.hdr) & F_DONE)) return;
+  int r0, r1;
+  block_rows(n, r0, r1);
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) y[r] = (double)x[r];
+}
+
 __global__ void k_fill64(int n, double* __restrict__ x, double v) {
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) x[i] = v;
 }

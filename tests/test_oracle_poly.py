@@ -104,3 +104,44 @@ def test_right_preconditioned_ir_converges_with_true_residual():
     assert pre.rel_resid <= 1e-10
     assert pre.iters < plain.iters
     assert np.linalg.norm(b - A.scipy() @ pre.x) / np.linalg.norm(b) == pytest.approx(pre.rel_resid)
+
+
+# ---------------------------------------------------------------------------
+# fp32 polynomial inside fp64 GMRES (Section "Preconditioning", an fp32 M
+# applied to fp64 vectors)
+# ---------------------------------------------------------------------------
+
+def _laplace3d(n):
+    A = P.stencil_matrix("laplace3d_7", n)
+    u = np.random.default_rng(0).uniform(-1, 1, A.n)
+    return A, A.scipy() @ u
+
+
+@pytest.mark.parametrize("d", [10, 40])
+def test_fp32_polynomial_in_fp64_gmres(d):
+    """The paper reports that with the polynomial applied in fp32 and all
+    else in fp64 the implicit (Givens) residual parts from the explicit one:
+    here the first cycle's implicit residual meets 1e-10 while the explicit
+    residual of its iterate stays above 1e-8; with the polynomial in fp64 the
+    two agree.  Restarts from the explicit residual still reach 1e-10."""
+    A, b = _laplace3d(12)
+    roots = PO.poly_roots(A, d, seed=12345)
+    r64 = L.gmres_ir(A, b, m=50, rtol=1e-10, inner="fp64", poly_roots=roots, check_mode=1)
+    assert r64.status == L.OK and r64.refinements == 1 and r64.outer[1] <= 1e-10
+    mix = L.gmres_ir(A, b, m=50, rtol=1e-10, inner="fp64", poly_roots=roots, poly_prec="fp32", check_mode=1)
+    first_implicit = mix.hist[mix.cycle_starts[1] - 1]
+    assert first_implicit <= 1e-10
+    assert mix.outer[1] >= 1e-8
+    assert mix.status == L.OK and mix.rel_resid <= 1e-10 and mix.refinements >= 2
+
+
+def test_fp32_polynomial_apply_is_fp32_accurate():
+    A, _ = _laplace3d(10)
+    roots = PO.poly_roots(A, 10, seed=1)
+    v = np.random.default_rng(2).standard_normal(A.n)
+    M64 = L.csr_matrix(A, np.float64)
+    M32 = L.csr_matrix(A, np.float32)
+    y64 = PO.apply_product_form(M64, roots, v, np.float64)
+    y32 = PO.apply_product_form(M32, roots, v.astype(np.float32), np.float32).astype(np.float64)
+    err = np.linalg.norm(y32 - y64) / np.linalg.norm(y64)
+    assert 1e-9 < err < 1e-4
