@@ -264,9 +264,33 @@ def gmres(A, b, x0=None, m=50, rtol=1e-10, max_iters=100000, check_mode=0, keep_
     return res
 
 
+def block_jacobi_inverses(A, bs: int) -> list:
+    """fp64 inverses of the diagonal blocks of ``A``: rows and columns
+    ``[k bs, (k+1) bs)`` (the last block ragged).  Block-Jacobi preconditioning
+    is named in the paper's Section "Preconditioning" and conclusions."""
+    S = A.scipy().tocsr()
+    out = []
+    for r0 in range(0, A.n, bs):
+        r1 = min(A.n, r0 + bs)
+        out.append(np.linalg.inv(S[r0:r1, r0:r1].toarray()))
+    return out
+
+
+def block_jacobi_apply(inverses, v: np.ndarray, dtype) -> np.ndarray:
+    """``M^{-1} v`` block by block in ``dtype`` with the inverses rounded to fp32."""
+    v = np.asarray(v, dtype=dtype)
+    y = np.empty_like(v)
+    r0 = 0
+    for Bi in inverses:
+        k = Bi.shape[0]
+        y[r0:r0 + k] = Bi.astype(np.float32).astype(dtype) @ v[r0:r0 + k]
+        r0 += k
+    return y
+
+
 def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
              max_iters=100000, check_mode=0, poly_roots=None, keep_iterates=False, max_refinements=0,
-             poly_prec=None):
+             poly_prec=None, bj_block=0):
     """GMRES-IR (Algorithm 2): fp64 residual and update around an inner GMRES(m).
 
     ``inner`` is ``"fp32"`` or ``"fp64"``; ``basis`` is ``"same"`` or ``"bf16"``
@@ -281,6 +305,9 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
     (Section "Preconditioning": each application of an fp32 ``M`` to an fp64
     vector casts it to fp32, multiplies by ``M`` with the fp32 matrix and
     casts the result back); every other operation stays in fp64.
+    ``bj_block > 0``: right block-Jacobi preconditioning instead, with the
+    fp64 inverses of the diagonal blocks rounded to fp32 and applied in the
+    inner precision.
     """
     wp = np.float32 if inner == "fp32" else np.float64
     if basis == "bf16" and wp != np.float32:
@@ -305,6 +332,9 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
                                                   np.float32).astype(np.float64)
         else:
             papply = lambda v: apply_product_form(Min, poly_roots, v, wp)
+    elif bj_block > 0:
+        inverses = block_jacobi_inverses(A, bj_block)
+        papply = lambda v: block_jacobi_apply(inverses, v, wp)
     else:
         papply = None
     op = (lambda v: spmv(Min, papply(v))) if papply else (lambda v: spmv(Min, v))

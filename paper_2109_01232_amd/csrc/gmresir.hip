@@ -152,10 +152,11 @@ int grid_spmv_part(const gmresir_matrix* A, const void* kern, size_t smem) {
 // ---------------------------------------------------------------------------
 
 struct Layout {
-  size_t V, wtmp, w1, w2, r64, rhat, u, z, py, p0, p1, p2, part, hdr, arr, total;
+  size_t V, wtmp, w1, w2, r64, rhat, u, z, py, p0, p1, p2, minv, part, hdr, arr, total;
   long ldv;
   int m;
   int sT, sS;
+  int bj;  // block-Jacobi block size (0: none)
   bool multi, poly;
 };
 
@@ -174,6 +175,9 @@ bool valid_params(const gmresir_params* p, const char** why) {
   if (p->check_mode != 0 && p->check_mode != 1) return *why = "check_mode must be 0 or 1", false;
   if (p->profile != 0 && p->profile != 1) return *why = "profile must be 0 or 1", false;
   if (p->poly_prec != 0 && p->poly_prec != GMRESIR_FP32) return *why = "poly_prec must be 0 or FP32", false;
+  if (p->bj_block < 0 || p->bj_block > BJ_MAX) return *why = "bj_block must be in [0, 32]", false;
+  if (p->bj_block > 0 && p->poly_degree > 0) return *why = "bj_block and poly_degree exclude each other", false;
+  if (p->reserved != 0) return *why = "reserved must be 0", false;
   return true;
 }
 
@@ -185,6 +189,7 @@ Layout make_layout(int64_t n, const gmresir_params* p) {
   int cap = p->inner_cap == 0 ? p->restart : p->inner_cap;
   L.multi = cap > p->restart;
   L.poly = p->poly_degree > 0;
+  L.bj = p->bj_block;
   L.ldv = (long)((n + 127) / 128 * 128);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -199,11 +204,12 @@ Layout make_layout(int64_t n, const gmresir_params* p) {
   L.w1 = take(vecT);
   L.w2 = take(vecT);
   L.r64 = take((size_t)L.ldv * 8);
-  bool need_uz = L.multi || L.poly;
+  bool need_uz = L.multi || L.poly || L.bj > 0;
   L.rhat = L.multi ? take(vecT) : 0;
   L.u = L.multi ? take(vecT) : 0;
   L.z = need_uz ? take(vecT) : 0;
-  L.py = L.poly ? take(vecT) : 0;
+  L.py = (L.poly || L.bj > 0) ? take(vecT) : 0;
+  L.minv = L.bj > 0 ? take((size_t)((n + L.bj - 1) / L.bj) * L.bj * L.bj * sizeof(float)) : 0;
   L.p0 = L.poly ? take(vecT) : 0;
   L.p1 = L.poly ? take(vecT) : 0;
   L.p2 = L.poly ? take(vecT) : 0;
@@ -459,6 +465,7 @@ struct Ctx {
   Prof* prof;
   std::vector<PStep> prog;
   bool poly_on = false;  // inner operator is A p(A)
+  float* minv = nullptr;  // block-Jacobi inverses (L.bj > 0): inner operator A M^{-1}
   // fp32 polynomial inside an fp64 inner solve: its buffers are carved from
   // the fp64 polynomial buffers (ldv fp32 entries each; two per buffer)
   bool poly32 = false;
@@ -475,8 +482,9 @@ struct Ctx {
     r64 = (double*)(ws + L.r64);
     rhat = L.multi ? (T*)(ws + L.rhat) : nullptr;
     u = L.multi ? (T*)(ws + L.u) : nullptr;
-    z = (L.multi || L.poly) ? (T*)(ws + L.z) : nullptr;
-    py = L.poly ? (T*)(ws + L.py) : nullptr;
+    z = (L.multi || L.poly || L.bj > 0) ? (T*)(ws + L.z) : nullptr;
+    py = (L.poly || L.bj > 0) ? (T*)(ws + L.py) : nullptr;
+    minv = L.bj > 0 ? (float*)(ws + L.minv) : nullptr;
     p0 = L.poly ? (T*)(ws + L.p0) : nullptr;
     p1 = L.poly ? (T*)(ws + L.p1) : nullptr;
     p2 = L.poly ? (T*)(ws + L.p2) : nullptr;
@@ -591,6 +599,34 @@ struct Ctx {
       int g = grid_spmv(A);
       prof->launch(cat, b, kern, dim3(g), dim3(BLOCK), lds, stream, A32, (const float*)X, (float*)nullptr, L.ldv, 0, 0,
                    (const float*)W, 0, y_out, D, cf, st, check_done, (const float*)nullptr, 0);
+    }
+  }
+
+  // block-Jacobi inverses from the fp64 CSR arrays (once per solve)
+  void bj_setup() {
+    const long nblk = ((long)n + L.bj - 1) / L.bj;
+    const double b = 12.0 * A->nnz + 4.0 * (n + 1) + 4.0 * nblk * L.bj * L.bj;
+    prof->launch(GMRESIR_CAT_OTHER, b, k_bj_invert, dim3((unsigned)nblk), dim3(WAVE), 0, stream, n,
+                 (const int*)A64.rowptr, (const int*)A64.col, (const double*)A64.vals, L.bj, minv);
+  }
+
+  int bj_grid() const {
+    const long nblk = ((long)n + L.bj - 1) / L.bj;
+    const long g = (nblk + NWAVES - 1) / NWAVES;
+    return (int)std::min<long>(g, 1L << 20);
+  }
+
+  // y = M^{-1} src; scaled: src is wtmp, v_j = round(wtmp * inv) also goes into V[:, j]
+  void bj_apply(const T* src, bool scaled, int j, T* y_out, int check_done, int cat, int nB = 0) {
+    const double b = 4.0 * n * L.bj + sT() * n * 2 + (scaled ? sS() * n : 0.0);
+    if (scaled) {
+      auto kern = k_bj_apply<T, S, true>;
+      prof->launch(cat, b, kern, dim3(bj_grid()), dim3(BLOCK), 0, stream, n, L.bj, (const float*)minv, src, V, L.ldv,
+                   j, y_out, st, check_done, (const T*)norm_part(), nB);
+    } else {
+      auto kern = k_bj_apply<T, S, false>;
+      prof->launch(cat, b, kern, dim3(bj_grid()), dim3(BLOCK), 0, stream, n, L.bj, (const float*)minv, src, V, L.ldv,
+                   j, y_out, st, check_done, (const T*)norm_part(), 0);
     }
   }
 
@@ -726,7 +762,10 @@ struct Ctx {
     const int nB = j > 0 ? norm_grid() : 0;
     prof->tag = j;
     prof->early = true;
-    if (poly_on && poly32) {
+    if (L.bj > 0) {
+      bj_apply(wtmp, true, j, z, 1, GMRESIR_CAT_POLY, nB);
+      spmv_proj_dispatch<false>(z, j, kmax, nB);
+    } else if (poly_on && poly32) {
       auto kern = k_scale_narrow<T, S>;
       int g = grid_rows((const void*)kern, n);
       prof->launch(GMRESIR_CAT_POLY, sT() * n + sS() * n + 4.0 * n, kern, dim3(g), dim3(BLOCK), 0, stream, n,
@@ -915,7 +954,12 @@ int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresi
   const bool single = cap <= m;
   int64_t hist_n = 0;
 
+  if (L.bj > 0 && (!c.z || !c.py || !c.minv)) {
+    set_error("internal: block-Jacobi buffers missing from the workspace layout");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
   c.init(p->rtol, p->check_mode, 0.0);
+  if (L.bj > 0) c.bj_setup();
   c.norm64(b, &c.st.hdr->beta);
   c.resid64(x, b);
   c.cast(c.r64);
@@ -959,12 +1003,15 @@ int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresi
       const int kmax = (int)std::min<int64_t>(m, budget - used);
       c.run_cycle(kmax);
       c.backsolve(kmax);
-      if (single && !L.poly) {
+      if (single && !L.poly && L.bj == 0) {
         c.correct_x(x, kmax);
       } else {
         c.vy(c.z, kmax);
         T* upart = c.z;
-        if (L.poly && c.poly32) {
+        if (L.bj > 0) {
+          c.bj_apply(c.z, false, 0, c.py, 0, GMRESIR_CAT_REFINE);
+          upart = c.py;
+        } else if (L.poly && c.poly32) {
           c.narrow((const double*)c.z, c.s32, 0, GMRESIR_CAT_REFINE);
           c.run_poly32(c.s32, c.y32, 0, GMRESIR_CAT_REFINE);
           c.widen(c.y32, (double*)c.py, 0, GMRESIR_CAT_REFINE);
@@ -1099,7 +1146,7 @@ bool fd_params(const gmresir_params* p, int64_t switch_iters, gmresir_params* q3
   if (!valid_params(p, why)) return false;
   if (p->inner_prec != GMRESIR_FP32) return *why = "GMRES-FD needs inner_prec FP32 (its first phase)", false;
   if (p->inner_cap != 0) return *why = "GMRES-FD needs inner_cap 0 (the switch point sets phase one)", false;
-  if (p->poly_degree != 0) return *why = "GMRES-FD takes no polynomial preconditioner", false;
+  if (p->poly_degree != 0 || p->bj_block != 0) return *why = "GMRES-FD takes no preconditioner", false;
   if (switch_iters < 0 || switch_iters > INT32_MAX) return *why = "switch_iters must be in [0, 2^31)", false;
   *q32 = *p;
   q32->inner_cap = (int32_t)std::max<int64_t>(switch_iters, 1);
@@ -1133,7 +1180,7 @@ void add_result(gmresir_result* acc, const gmresir_result& r) {
 
 extern "C" {
 
-int32_t gmresir_abi_version(void) { return 2; }
+int32_t gmresir_abi_version(void) { return 3; }
 
 const char* gmresir_last_error(void) { return gir::last_error(); }
 

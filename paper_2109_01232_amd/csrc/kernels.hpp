@@ -1242,6 +1242,112 @@ __global__ __launch_bounds__(BLOCK) void k_widen(int n, const float* __restrict_
   for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) y[r] = (double)x[r];
 }
 
+// ---------------------------------------------------------------------------
+// block Jacobi preconditioner: M = blockdiag(A_11, A_22, ...), blocks of
+// bs <= 32 consecutive rows/columns (the last one ragged)
+// ---------------------------------------------------------------------------
+
+constexpr int BJ_MAX = 32;
+
+// One wave per diagonal block: the block is gathered from the fp64 CSR
+// arrays into LDS next to an identity, reduced by Gauss-Jordan elimination
+// with partial pivoting in fp64, and its inverse written rounded to fp32,
+// column-major with leading dimension bs: Minv[blk][c][i] = inv(A_bb)[i][c].
+// A zero or non-finite pivot writes NaN (the solve then reports NUMERIC).
+__global__ __launch_bounds__(WAVE) void k_bj_invert(int n, const int* __restrict__ rowptr,
+                                                    const int* __restrict__ col, const double* __restrict__ vals,
+                                                    int bs, float* __restrict__ Minv) {
+  __shared__ double a[BJ_MAX][2 * BJ_MAX + 1];
+  __shared__ int s_piv;
+  const int i = threadIdx.x;
+  const long r0 = (long)blockIdx.x * bs;
+  const int m = (int)((n - r0) < bs ? (n - r0) : bs);
+  if (i < BJ_MAX)
+    for (int c = 0; c < 2 * BJ_MAX; ++c) a[i][c] = (i < m && c == m + i) ? 1.0 : 0.0;
+  if (i < m) {
+    const long r = r0 + i;
+    for (int q = rowptr[r]; q < rowptr[r + 1]; ++q) {
+      const long c = col[q] - r0;
+      if (c >= 0 && c < m) a[i][c] = vals[q];
+    }
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int k = 0; k < m; ++k) {
+    if (i == 0) {
+      int p = k;
+      double best = fabs(a[k][k]);
+      for (int q = k + 1; q < m; ++q)
+        if (fabs(a[q][k]) > best) best = fabs(a[q][k]), p = q;
+      s_piv = p;
+    }
+    __syncthreads();
+    const int p = s_piv;
+    if (p != k) {
+      for (int c = i; c < 2 * m; c += WAVE) {
+        const double t = a[k][c];
+        a[k][c] = a[p][c];
+        a[p][c] = t;
+      }
+    }
+    __syncthreads();
+    const double piv = a[k][k];
+    bad = bad || !(fabs(piv) > 0.0) || !isfinite(piv);
+    __syncthreads();
+    for (int c = i; c < 2 * m; c += WAVE) a[k][c] = a[k][c] / piv;
+    __syncthreads();
+    if (i < m && i != k) {
+      const double f = a[i][k];
+      for (int c = 0; c < 2 * m; ++c) a[i][c] -= f * a[k][c];
+    }
+    __syncthreads();
+  }
+  const float nan = __builtin_nanf("");
+  float* out = Minv + (size_t)blockIdx.x * bs * bs;
+  if (i < m)
+    for (int c = 0; c < m; ++c) out[(size_t)c * bs + i] = bad ? nan : (float)a[i][m + c];
+}
+
+// y = M^{-1} x, one wave per diagonal block (lane = row of the block).
+// SCALED: x is the next basis vector v_j = round(wtmp * inv), which is also
+// stored as basis column j (the fused start of an iteration, as in the
+// polynomial path).  check_done as in the other iteration kernels.
+template <typename T, typename S, bool SCALED>
+__global__ __launch_bounds__(BLOCK) void k_bj_apply(int n, int bs, const float* __restrict__ Minv,
+                                                    const T* __restrict__ src, S* __restrict__ V, long ldv, int j,
+                                                    T* __restrict__ y, State st, int check_done,
+                                                    const T* __restrict__ norm_part, int nB) {
+  __shared__ T s_x[NWAVES][BJ_MAX];
+  const int flags = check_done ? load_flags(st.hdr) : 0;
+  const T inv = SCALED ? prev_inv_norm<T>(st, norm_part, nB) : T(1);
+  if (flags & F_DONE) return;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  const long nblk = ((long)n + bs - 1) / bs;
+  for (long blk = (long)blockIdx.x * NWAVES + wid; blk < nblk; blk += (long)gridDim.x * NWAVES) {
+    const long r0 = blk * bs;
+    const int m = (int)((n - r0) < bs ? (n - r0) : bs);
+    T xv = T(0);
+    if (lane < m) {
+      if (SCALED) {
+        xv = Basis<S, T>::round(src[r0 + lane] * inv);
+        Basis<S, T>::store(V + (size_t)j * ldv + r0 + lane, xv);
+      } else {
+        xv = src[r0 + lane];
+      }
+    }
+    if (lane < BJ_MAX) s_x[wid][lane] = xv;
+    __builtin_amdgcn_wave_barrier();
+    if (lane < m) {
+      const float* Mb = Minv + (size_t)blk * bs * bs;
+      T acc = T(0);
+      for (int c = 0; c < m; ++c) acc += (T)Mb[(size_t)c * bs + lane] * s_x[wid][c];
+      y[r0 + lane] = acc;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 __global__ void k_fill64(int n, double* __restrict__ x, double v) {
   for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) x[i] = v;
 }
