@@ -301,7 +301,7 @@ def main():
         # GMRES-IR with a right block-Jacobi preconditioner (fp32 inverses of
         # the diagonal blocks, built at the start of every solve: included)
         bj = []
-        for bs in (8, 16, 32):
+        for bs in (8, 16, 32, 42, 64):
             p_bj = B.make_params(restart=args.restart, inner="fp32", basis=args.basis, rtol=1e-10, check_mode=1,
                                  bj_block=bs)
             x.zero_()

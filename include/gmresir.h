@@ -92,7 +92,7 @@ typedef struct {
                           (Section "Preconditioning", the case of an fp32 M applied to fp64 vectors:
                           each application casts its fp64 input to fp32, runs the d fp32 SpMV steps on
                           the fp32 copy of A and widens the result; every other operation stays fp64) */
-  int32_t bj_block;    /* 0: none; 1..32: right block-Jacobi preconditioner M = blockdiag of the
+  int32_t bj_block;    /* 0: none; 1..64: right block-Jacobi preconditioner M = blockdiag of the
                           diagonal blocks of A of bj_block consecutive rows (the last one ragged),
                           inverted in fp64 by Gauss-Jordan elimination with partial pivoting at the
                           start of every solve and stored rounded to fp32; applied in the inner

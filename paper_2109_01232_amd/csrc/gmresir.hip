@@ -175,7 +175,7 @@ bool valid_params(const gmresir_params* p, const char** why) {
   if (p->check_mode != 0 && p->check_mode != 1) return *why = "check_mode must be 0 or 1", false;
   if (p->profile != 0 && p->profile != 1) return *why = "profile must be 0 or 1", false;
   if (p->poly_prec != 0 && p->poly_prec != GMRESIR_FP32) return *why = "poly_prec must be 0 or FP32", false;
-  if (p->bj_block < 0 || p->bj_block > BJ_MAX) return *why = "bj_block must be in [0, 32]", false;
+  if (p->bj_block < 0 || p->bj_block > BJ_MAX) return *why = "bj_block must be in [0, 64]", false;
   if (p->bj_block > 0 && p->poly_degree > 0) return *why = "bj_block and poly_degree exclude each other", false;
   if (p->reserved != 0) return *why = "reserved must be 0", false;
   return true;

@@ -1244,13 +1244,14 @@ __global__ __launch_bounds__(BLOCK) void k_widen(int n, const float* __restrict_
 
 // ---------------------------------------------------------------------------
 // block Jacobi preconditioner: M = blockdiag(A_11, A_22, ...), blocks of
-// bs <= 32 consecutive rows/columns (the last one ragged)
+// bs <= 64 consecutive rows/columns (the last one ragged)
 // ---------------------------------------------------------------------------
 
-constexpr int BJ_MAX = 32;
+constexpr int BJ_MAX = 64;
 
 // One wave per diagonal block: the block is gathered from the fp64 CSR
-// arrays into LDS next to an identity, reduced by Gauss-Jordan elimination
+// arrays into LDS next to an identity (66 KB of LDS at bs = 64: gfx950
+// gives a workgroup up to 160 KB), reduced by Gauss-Jordan elimination
 // with partial pivoting in fp64, and its inverse written rounded to fp32,
 // column-major with leading dimension bs: Minv[blk][c][i] = inv(A_bb)[i][c].
 // A zero or non-finite pivot writes NaN (the solve then reports NUMERIC).

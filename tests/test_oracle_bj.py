@@ -22,7 +22,7 @@ def test_block_size_one_is_jacobi():
     assert np.array_equal(y, (1.0 / d).astype(np.float32).astype(np.float64) * v)
 
 
-@pytest.mark.parametrize("bs", [7, 16, 32])
+@pytest.mark.parametrize("bs", [7, 16, 42, 64])
 def test_inverses_invert_the_diagonal_blocks(bs):
     s = P.parity_system()
     S = s.A.scipy().tocsr()
