@@ -612,7 +612,9 @@ struct Ctx {
 
   int bj_grid() const {
     const long nblk = ((long)n + L.bj - 1) / L.bj;
-    const long g = (nblk + NWAVES - 1) / NWAVES;
+    const long per_wave = WAVE / L.bj;  // blocks a wave takes at once
+    const long ngrp = (nblk + per_wave - 1) / per_wave;
+    const long g = (ngrp + NWAVES - 1) / NWAVES;
     return (int)std::min<long>(g, 1L << 20);
   }
 

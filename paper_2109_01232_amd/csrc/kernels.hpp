@@ -1309,7 +1309,10 @@ __global__ __launch_bounds__(WAVE) void k_bj_invert(int n, const int* __restrict
     for (int c = 0; c < m; ++c) out[(size_t)c * bs + i] = bad ? nan : (float)a[i][m + c];
 }
 
-// y = M^{-1} x, one wave per diagonal block (lane = row of the block).
+// y = M^{-1} x.  A wave takes G = 64 / bs consecutive diagonal blocks at
+// once (lane = g * bs + i: row i of block g; for bs = 8 all 64 lanes work),
+// stages their x in LDS and each lane sums its row of the inverse over the
+// block's columns in ascending order (column reads of a block are contiguous).
 // SCALED: x is the next basis vector v_j = round(wtmp * inv), which is also
 // stored as basis column j (the fused start of an iteration, as in the
 // polynomial path).  check_done as in the other iteration kernels.
@@ -1318,32 +1321,38 @@ __global__ __launch_bounds__(BLOCK) void k_bj_apply(int n, int bs, const float* 
                                                     const T* __restrict__ src, S* __restrict__ V, long ldv, int j,
                                                     T* __restrict__ y, State st, int check_done,
                                                     const T* __restrict__ norm_part, int nB) {
-  __shared__ T s_x[NWAVES][BJ_MAX];
+  __shared__ T s_x[NWAVES][WAVE];
   const int flags = check_done ? load_flags(st.hdr) : 0;
   const T inv = SCALED ? prev_inv_norm<T>(st, norm_part, nB) : T(1);
   if (flags & F_DONE) return;
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = threadIdx.x / WAVE;
+  const int G = WAVE / bs;  // blocks per wave, >= 1 for bs <= 64
+  const int g = lane / bs;
+  const int i = lane - g * bs;
   const long nblk = ((long)n + bs - 1) / bs;
-  for (long blk = (long)blockIdx.x * NWAVES + wid; blk < nblk; blk += (long)gridDim.x * NWAVES) {
+  const long ngrp = (nblk + G - 1) / G;
+  for (long grp = (long)blockIdx.x * NWAVES + wid; grp < ngrp; grp += (long)gridDim.x * NWAVES) {
+    const long blk = grp * G + g;
     const long r0 = blk * bs;
-    const int m = (int)((n - r0) < bs ? (n - r0) : bs);
+    const int m = (g < G && blk < nblk) ? (int)((n - r0) < bs ? (n - r0) : bs) : 0;
     T xv = T(0);
-    if (lane < m) {
+    if (i < m) {
       if (SCALED) {
-        xv = Basis<S, T>::round(src[r0 + lane] * inv);
-        Basis<S, T>::store(V + (size_t)j * ldv + r0 + lane, xv);
+        xv = Basis<S, T>::round(src[r0 + i] * inv);
+        Basis<S, T>::store(V + (size_t)j * ldv + r0 + i, xv);
       } else {
-        xv = src[r0 + lane];
+        xv = src[r0 + i];
       }
     }
-    if (lane < BJ_MAX) s_x[wid][lane] = xv;
+    s_x[wid][lane] = xv;
     __builtin_amdgcn_wave_barrier();
-    if (lane < m) {
+    if (i < m) {
       const float* Mb = Minv + (size_t)blk * bs * bs;
+      const T* xs = &s_x[wid][g * bs];
       T acc = T(0);
-      for (int c = 0; c < m; ++c) acc += (T)Mb[(size_t)c * bs + lane] * s_x[wid][c];
-      y[r0 + lane] = acc;
+      for (int c = 0; c < m; ++c) acc += (T)Mb[(size_t)c * bs + i] * xs[c];
+      y[r0 + i] = acc;
     }
     __builtin_amdgcn_wave_barrier();
   }
