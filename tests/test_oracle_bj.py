@@ -14,10 +14,10 @@ from paper_2109_01232_amd import problems as P
 
 
 def test_block_size_one_is_jacobi():
-    s = P.parity_system()
-    inv = L.block_jacobi_inverses(s.A, 1)
-    d = s.A.scipy().diagonal()
-    v = np.random.default_rng(0).standard_normal(s.A.n)
+    A = P.conv_diff(3, 9, 10.0, (1, 1, 1), (1, 1, 1e-2))  # diagonal 4.02: 1/d is rounded in fp32
+    inv = L.block_jacobi_inverses(A, 1)
+    d = A.scipy().diagonal()
+    v = np.random.default_rng(0).standard_normal(A.n)
     y = L.block_jacobi_apply(inv, v, np.float64)
     assert np.array_equal(y, (1.0 / d).astype(np.float32).astype(np.float64) * v)
 
