@@ -605,8 +605,10 @@ struct Ctx {
   // block-Jacobi inverses from the fp64 CSR arrays (once per solve)
   void bj_setup() {
     const long nblk = ((long)n + L.bj - 1) / L.bj;
+    const long per_wave = WAVE / L.bj;  // blocks a wave inverts together
+    const long grid = (nblk + per_wave - 1) / per_wave;
     const double b = 12.0 * A->nnz + 4.0 * (n + 1) + 4.0 * nblk * L.bj * L.bj;
-    prof->launch(GMRESIR_CAT_OTHER, b, k_bj_invert, dim3((unsigned)nblk), dim3(WAVE), 0, stream, n,
+    prof->launch(GMRESIR_CAT_OTHER, b, k_bj_invert, dim3((unsigned)grid), dim3(WAVE), 0, stream, n,
                  (const int*)A64.rowptr, (const int*)A64.col, (const double*)A64.vals, L.bj, minv);
   }
 

@@ -1249,64 +1249,77 @@ __global__ __launch_bounds__(BLOCK) void k_widen(int n, const float* __restrict_
 
 constexpr int BJ_MAX = 64;
 
-// One wave per diagonal block: the block is gathered from the fp64 CSR
-// arrays into LDS next to an identity (66 KB of LDS at bs = 64: gfx950
-// gives a workgroup up to 160 KB), reduced by Gauss-Jordan elimination
-// with partial pivoting in fp64, and its inverse written rounded to fp32,
-// column-major with leading dimension bs: Minv[blk][c][i] = inv(A_bb)[i][c].
-// A zero or non-finite pivot writes NaN (the solve then reports NUMERIC).
+// One wave inverts G = 64 / bs consecutive diagonal blocks (lane = g * bs + i:
+// row i of block g).  Each block is gathered from the fp64 CSR arrays into
+// LDS next to an identity (66 KB of LDS: gfx950 gives a workgroup up to
+// 160 KB), reduced by Gauss-Jordan elimination with partial pivoting in fp64,
+// and its inverse written rounded to fp32, column-major with leading
+// dimension bs: Minv[blk][c][i] = inv(A_bb)[i][c].  The bs pivot steps run
+// in lock step for all blocks of the wave (a ragged last block skips the
+// steps beyond its size).  A zero or non-finite pivot writes NaN (the solve
+// then reports NUMERIC).
 __global__ __launch_bounds__(WAVE) void k_bj_invert(int n, const int* __restrict__ rowptr,
                                                     const int* __restrict__ col, const double* __restrict__ vals,
                                                     int bs, float* __restrict__ Minv) {
-  __shared__ double a[BJ_MAX][2 * BJ_MAX + 1];
-  __shared__ int s_piv;
-  const int i = threadIdx.x;
-  const long r0 = (long)blockIdx.x * bs;
-  const int m = (int)((n - r0) < bs ? (n - r0) : bs);
-  if (i < BJ_MAX)
-    for (int c = 0; c < 2 * BJ_MAX; ++c) a[i][c] = (i < m && c == m + i) ? 1.0 : 0.0;
+  __shared__ double a[WAVE][2 * BJ_MAX + 1];
+  __shared__ int s_piv[WAVE];
+  const int lane = threadIdx.x;
+  const int G = WAVE / bs;
+  const int g = lane / bs;
+  const int i = lane - g * bs;
+  const long nblk = ((long)n + bs - 1) / bs;
+  const long blk = (long)blockIdx.x * G + g;
+  const long r0 = blk * bs;
+  const int m = (g < G && blk < nblk) ? (int)((n - r0) < bs ? (n - r0) : bs) : 0;
+  const int base = g * bs;  // first LDS row of this lane's block
+  for (int c = 0; c < 2 * BJ_MAX; ++c) a[lane][c] = (i < m && c == m + i) ? 1.0 : 0.0;
   if (i < m) {
     const long r = r0 + i;
     for (int q = rowptr[r]; q < rowptr[r + 1]; ++q) {
       const long c = col[q] - r0;
-      if (c >= 0 && c < m) a[i][c] = vals[q];
+      if (c >= 0 && c < m) a[lane][c] = vals[q];
     }
   }
   __syncthreads();
   bool bad = false;
-  for (int k = 0; k < m; ++k) {
-    if (i == 0) {
+  for (int k = 0; k < bs; ++k) {
+    const bool act = k < m;
+    if (act && i == 0) {
       int p = k;
-      double best = fabs(a[k][k]);
+      double best = fabs(a[base + k][k]);
       for (int q = k + 1; q < m; ++q)
-        if (fabs(a[q][k]) > best) best = fabs(a[q][k]), p = q;
-      s_piv = p;
+        if (fabs(a[base + q][k]) > best) best = fabs(a[base + q][k]), p = q;
+      s_piv[g] = p;
     }
     __syncthreads();
-    const int p = s_piv;
-    if (p != k) {
-      for (int c = i; c < 2 * m; c += WAVE) {
-        const double t = a[k][c];
-        a[k][c] = a[p][c];
-        a[p][c] = t;
+    if (act) {
+      const int p = s_piv[g];
+      if (p != k) {
+        for (int c = i; c < 2 * m; c += bs) {
+          const double t = a[base + k][c];
+          a[base + k][c] = a[base + p][c];
+          a[base + p][c] = t;
+        }
       }
     }
     __syncthreads();
-    const double piv = a[k][k];
-    bad = bad || !(fabs(piv) > 0.0) || !isfinite(piv);
+    const double piv = act ? a[base + k][k] : 1.0;
+    if (act) bad = bad || !(fabs(piv) > 0.0) || !isfinite(piv);
     __syncthreads();
-    for (int c = i; c < 2 * m; c += WAVE) a[k][c] = a[k][c] / piv;
+    if (act)
+      for (int c = i; c < 2 * m; c += bs) a[base + k][c] = a[base + k][c] / piv;
     __syncthreads();
-    if (i < m && i != k) {
-      const double f = a[i][k];
-      for (int c = 0; c < 2 * m; ++c) a[i][c] -= f * a[k][c];
+    if (act && i < m && i != k) {
+      const double f = a[lane][k];
+      for (int c = 0; c < 2 * m; ++c) a[lane][c] -= f * a[base + k][c];
     }
     __syncthreads();
   }
   const float nan = __builtin_nanf("");
-  float* out = Minv + (size_t)blockIdx.x * bs * bs;
-  if (i < m)
-    for (int c = 0; c < m; ++c) out[(size_t)c * bs + i] = bad ? nan : (float)a[i][m + c];
+  if (i < m) {
+    float* out = Minv + (size_t)blk * bs * bs;
+    for (int c = 0; c < m; ++c) out[(size_t)c * bs + i] = bad ? nan : (float)a[lane][m + c];
+  }
 }
 
 // y = M^{-1} x.  A wave takes G = 64 / bs consecutive diagonal blocks at
