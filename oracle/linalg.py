@@ -264,11 +264,18 @@ def gmres(A, b, x0=None, m=50, rtol=1e-10, max_iters=100000, check_mode=0, keep_
     return res
 
 
-def block_jacobi_inverses(A, bs: int) -> list:
-    """fp64 inverses of the diagonal blocks of ``A``: rows and columns
-    ``[k bs, (k+1) bs)`` (the last block ragged).  Block-Jacobi preconditioning
-    is named in the paper's Section "Preconditioning" and conclusions."""
-    S = A.scipy().tocsr()
+def block_jacobi_inverses(A, bs: int, dtype=np.float64) -> list:
+    """Inverses of the diagonal blocks of ``A`` (rows and columns
+    ``[k bs, (k+1) bs)``, the last block ragged), computed in ``dtype`` from
+    the matrix rounded to ``dtype`` (LAPACK LU inverse in that precision).
+
+    Block-Jacobi preconditioning is named in Sections "Preconditioning" and
+    "SpMV Speedup: A Large Test Set"; for GMRES-IR (case (b) of Section
+    "Preconditioning") the fp32 preconditioner is both computed and applied in
+    fp32, so the inner solve of GMRES-IR takes ``dtype = float32``; the fp64
+    solve keeps an fp64 preconditioner.
+    """
+    S = csr_matrix(A, dtype)
     out = []
     for r0 in range(0, A.n, bs):
         r1 = min(A.n, r0 + bs)
@@ -277,13 +284,13 @@ def block_jacobi_inverses(A, bs: int) -> list:
 
 
 def block_jacobi_apply(inverses, v: np.ndarray, dtype) -> np.ndarray:
-    """``M^{-1} v`` block by block in ``dtype`` with the inverses rounded to fp32."""
+    """``M^{-1} v`` block by block in ``dtype`` (the inverses' own precision)."""
     v = np.asarray(v, dtype=dtype)
     y = np.empty_like(v)
     r0 = 0
     for Bi in inverses:
         k = Bi.shape[0]
-        y[r0:r0 + k] = Bi.astype(np.float32).astype(dtype) @ v[r0:r0 + k]
+        y[r0:r0 + k] = Bi.astype(dtype, copy=False) @ v[r0:r0 + k]
         r0 += k
     return y
 
@@ -305,9 +312,8 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
     (Section "Preconditioning": each application of an fp32 ``M`` to an fp64
     vector casts it to fp32, multiplies by ``M`` with the fp32 matrix and
     casts the result back); every other operation stays in fp64.
-    ``bj_block > 0``: right block-Jacobi preconditioning instead, with the
-    fp64 inverses of the diagonal blocks rounded to fp32 and applied in the
-    inner precision.
+    ``bj_block > 0``: right block-Jacobi preconditioning instead, the inverses
+    of the diagonal blocks computed and applied in the inner precision.
     """
     wp = np.float32 if inner == "fp32" else np.float64
     if basis == "bf16" and wp != np.float32:
@@ -333,7 +339,7 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
         else:
             papply = lambda v: apply_product_form(Min, poly_roots, v, wp)
     elif bj_block > 0:
-        inverses = block_jacobi_inverses(A, bj_block)
+        inverses = block_jacobi_inverses(A, bj_block, wp)
         papply = lambda v: block_jacobi_apply(inverses, v, wp)
     else:
         papply = None

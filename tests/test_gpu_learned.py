@@ -29,7 +29,7 @@ def _gpu():
     B.lib()
 
 
-@pytest.mark.parametrize("case", ["cfg1", "aniso3d", "varcoef27", "chooser"])
+@pytest.mark.parametrize("case", ["cfg1", "aniso3d", "varcoef27", "chooser", "cyclic"])
 def test_features_match_oracle(case):
     if case == "cfg1":
         s = P.parity_system()
@@ -40,9 +40,14 @@ def test_features_match_oracle(case):
     elif case == "varcoef27":
         A = P.varcoef27(12, 2)
         b = A.scipy() @ np.random.default_rng(1).uniform(-1, 1, A.n)
-    else:
+    elif case == "chooser":
         sysm = P.chooser_system(5, n_max=3e4)
         A, b = sysm.A, sysm.b
+    else:
+        # seven known eigenvalues, exact fp32 Arnoldi ending in an exact breakdown
+        from test_oracle_features import cyclic_system
+
+        A, _, b = cyclic_system()
     say("features", case)
     M = B.Matrix.from_csr(A)
     got = B.gmresir_features(M, dev_tensor(b))

@@ -1,11 +1,16 @@
-"""Pins of the oracle's block-Jacobi preconditioner (right preconditioning
-inside GMRES-IR; blocks of consecutive rows, inverses in fp64 rounded to fp32).
+"""Pins of the oracle's block-Jacobi preconditioner (right preconditioning,
+blocks of consecutive rows, inverses computed and applied in the inner
+precision: Section "Preconditioning", case (b), computes and applies the fp32
+preconditioner of GMRES-IR entirely in fp32).
 
-Block size 1 is Jacobi (division by the diagonal); every block inverse
-times its block is the identity; one block covering the whole matrix makes
-M^{-1} the fp32-rounded inverse of A, so every inner cycle reaches fp32
-accuracy in a step or two; on the convection-diffusion parity system the
-preconditioner cuts the iteration count."""
+Block size 1 is Jacobi: in fp32 the inverse is the correctly rounded fp32
+quotient 1 / fl32(a_ii) (one IEEE division), which differs from the fp64
+quotient rounded to fp32 on some rows of a matrix with a varied diagonal;
+every block inverse times its block is the identity to the precision's
+accuracy; one block covering the whole matrix makes M^{-1} the inverse of A
+to fp32 accuracy, so every inner cycle stops in a step or two; on the
+convection-diffusion parity system the preconditioner cuts the iteration
+count."""
 import numpy as np
 import pytest
 
@@ -13,26 +18,51 @@ from oracle import linalg as L
 from paper_2109_01232_amd import problems as P
 
 
-def test_block_size_one_is_jacobi():
-    A = P.conv_diff(3, 9, 10.0, (1, 1, 1), (1, 1, 1e-2))  # diagonal 4.02: 1/d is rounded in fp32
-    inv = L.block_jacobi_inverses(A, 1)
-    d = A.scipy().diagonal()
-    v = np.random.default_rng(0).standard_normal(A.n)
-    y = L.block_jacobi_apply(inv, v, np.float64)
-    assert np.array_equal(y, (1.0 / d).astype(np.float32).astype(np.float64) * v)
+def varied_diagonal_system(n=2000, seed=0):
+    """A tridiagonal matrix whose diagonal entries are random (so that 1 / d
+    rounds differently in fp32 and fp64 on some rows)."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(3.0, 7.0, n)
+    S = sp.diags([np.full(n - 1, -1.0), d, np.full(n - 1, -1.3)], [-1, 0, 1], format="csr")
+    S.sort_indices()
+    return P.CSR(n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64)), d
+
+
+def test_block_size_one_is_jacobi_fp32():
+    A, d = varied_diagonal_system()
+    inv = L.block_jacobi_inverses(A, 1, np.float32)
+    assert all(Bi.dtype == np.float32 for Bi in inv)
+    v = np.random.default_rng(0).standard_normal(A.n).astype(np.float32)
+    y = L.block_jacobi_apply(inv, v, np.float32)
+    d32 = d.astype(np.float32)
+    want = (np.float32(1.0) / d32) * v  # fp32 division and product, each correctly rounded
+    assert np.array_equal(y, want)
+    # the fp32 computation is not the fp64 one rounded afterwards on every row
+    assert np.any((np.float32(1.0) / d32) != (1.0 / d).astype(np.float32))
+
+
+def test_block_size_one_is_jacobi_fp64():
+    A, d = varied_diagonal_system()
+    inv = L.block_jacobi_inverses(A, 1, np.float64)
+    v = np.random.default_rng(1).standard_normal(A.n)
+    assert np.array_equal(L.block_jacobi_apply(inv, v, np.float64), (1.0 / d) * v)
 
 
 @pytest.mark.parametrize("bs", [7, 16, 42, 64])
-def test_inverses_invert_the_diagonal_blocks(bs):
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 2e-6)])
+def test_inverses_invert_the_diagonal_blocks(bs, dtype, tol):
     s = P.parity_system()
     S = s.A.scipy().tocsr()
-    inv = L.block_jacobi_inverses(s.A, bs)
+    inv = L.block_jacobi_inverses(s.A, bs, dtype)
     assert len(inv) == -(-s.A.n // bs)
     r0 = 0
     for Bi in inv:
         k = Bi.shape[0]
+        assert Bi.dtype == dtype
         blk = S[r0:r0 + k, r0:r0 + k].toarray()
-        assert np.abs(Bi @ blk - np.eye(k)).max() <= 1e-12
+        assert np.abs(Bi.astype(np.float64) @ blk - np.eye(k)).max() <= tol
         r0 += k
     assert r0 == s.A.n
 

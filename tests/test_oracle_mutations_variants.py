@@ -45,19 +45,20 @@ def variant_pins(L):
         failed.append("fd (exception)")
     # block Jacobi
     try:
-        Aj = P.conv_diff(3, 8, 10.0, (1, 1, 1), (1, 1, 1e-2))  # diagonal 4.02: 1/d not exact in fp32
-        inv = L.block_jacobi_inverses(Aj, 1)
-        d = Aj.scipy().diagonal()
-        v = np.random.default_rng(0).standard_normal(Aj.n)
-        if not np.array_equal(L.block_jacobi_apply(inv, v, np.float64),
-                              (1.0 / d).astype(np.float32).astype(np.float64) * v):
-            failed.append("bj jacobi")
+        from test_oracle_bj import varied_diagonal_system
+
+        Aj, d = varied_diagonal_system()
+        inv = L.block_jacobi_inverses(Aj, 1, np.float32)
+        v = np.random.default_rng(0).standard_normal(Aj.n).astype(np.float32)
+        if not np.array_equal(L.block_jacobi_apply(inv, v, np.float32),
+                              (np.float32(1.0) / d.astype(np.float32)) * v):
+            failed.append("bj jacobi fp32")
         S = s.A.scipy().tocsr()
-        inv = L.block_jacobi_inverses(s.A, 16)
+        inv = L.block_jacobi_inverses(s.A, 16, np.float64)
         v = np.random.default_rng(1).standard_normal(s.A.n)
         y = L.block_jacobi_apply(inv, v, np.float64)
         blk = S[16:32, 16:32].toarray()
-        if not (len(inv) == 256 and np.abs(blk @ y[16:32] - v[16:32]).max() <= 1e-5 * np.abs(v[16:32]).max()):
+        if not (len(inv) == 256 and np.abs(blk @ y[16:32] - v[16:32]).max() <= 1e-12 * np.abs(v[16:32]).max()):
             failed.append("bj blocks")
         A, Ad, b = _tiny_dense()
         r = L.gmres_ir(A, b, m=20, rtol=1e-12, inner="fp32", bj_block=A.n, check_mode=1)
@@ -88,10 +89,14 @@ MUTATIONS = [
      "total.iters = double.iters"),
     ("fd: single phase in fp64", 'single = gmres_ir(A, b, m=m, rtol=rtol, inner="fp32"',
      'single = gmres_ir(A, b, m=m, rtol=rtol, inner="fp64"'),
-    ("bj: inverses not rounded to fp32", "y[r0:r0 + k] = Bi.astype(np.float32).astype(dtype) @ v[r0:r0 + k]",
-     "y[r0:r0 + k] = Bi.astype(dtype) @ v[r0:r0 + k]"),
-    ("bj: transposed inverse", "y[r0:r0 + k] = Bi.astype(np.float32).astype(dtype) @ v[r0:r0 + k]",
-     "y[r0:r0 + k] = Bi.T.astype(np.float32).astype(dtype) @ v[r0:r0 + k]"),
+    ("bj: fp32 inverses computed in fp64 and rounded", "S = csr_matrix(A, dtype)\n    out = []",
+     "S = csr_matrix(A, np.float64)\n    out = []"),
+    ("bj: transposed inverse", "y[r0:r0 + k] = Bi.astype(dtype, copy=False) @ v[r0:r0 + k]",
+     "y[r0:r0 + k] = Bi.T.astype(dtype) @ v[r0:r0 + k]"),
+    # (An inner solve given fp64 inverses rounded to fp32 instead of fp32 ones is
+    # not listed: the two preconditioners differ only at fp32 rounding level, so
+    # the solves differ at that level too; the fp32 computation itself is pinned
+    # bitwise at the function level by "bj jacobi fp32".)
     ("bj: overlapping blocks", "r1 = min(A.n, r0 + bs)", "r1 = min(A.n, r0 + bs + 1)"),
     ("poly32: polynomial left in fp64", 'if poly_prec == "fp32" and wp == np.float64:', "if False:"),
 ]
