@@ -185,6 +185,129 @@ def gmres_cycle(op, r, m, dtype=np.float64, basis="same", kmax=None, stop_abs=No
                  breakdown, stopped, numeric_error)
 
 
+def gmres_cycle_lowsync(op, r, m, dtype=np.float64, kmax=None, stop_abs=None) -> Cycle:
+    """One restart cycle of GMRES(m) whose Arnoldi process orthogonalises with
+    classical Gram-Schmidt twice, the second pass and the normalisation
+    delayed by one iteration so that each iteration needs one global reduction
+    (the "DCGS2" Arnoldi of Bielich, Langou, Thomas, Swirydowicz, Yamazaki and
+    Boman, "Low-synch Gram-Schmidt with delayed reorthogonalization for Krylov
+    solvers", Parallel Computing 112, 2022; the paper under study runs CGS2 as
+    two separate passes, Section "GMRES", and names the launch count of
+    unfused kernels as a cost, Section "Software Implementation").
+
+    Iteration j >= 1 starts from u_j, the vector of iteration j-1 after one
+    Gram-Schmidt pass against Q = [v_0 .. v_{j-1}] (not normalised), and from
+    p = A u_j.  One reduction gives a = Q^T u_j, alpha = u_j^T u_j,
+    c = Q^T p and gam = u_j^T p.  Then, in exact arithmetic the same as CGS2:
+
+    * second pass and norm of u_j: v_j = (u_j - Q a) / rho with
+      rho = sqrt(alpha - a^T a) (Pythagoras, Q orthonormal);
+    * Hessenberg column j-1 completed: H[:j, j-1] += a, H[j, j-1] = rho (then
+      its Givens rotation, the implicit residual and the stop tests, as in
+      gmres_cycle);
+    * A v_j = (p - A Q a) / rho and A Q = V_{j+1} H[:j+1, :j] (the Arnoldi
+      relation of the completed columns), so with t = H[:j+1, :j] a the first
+      pass of w = A v_j needs no further reduction:
+      h1_i = (c_i - t_i) / rho for i < j,
+      h1_j = ((gam - a^T c) / rho - t_j) / rho;
+    * u_{j+1} = w - V_{j+1} h1 = p / rho - V_{j+1} (t / rho + h1).
+
+    Iteration 0 is the first pass of w = A v_0 alone; the last iteration only
+    completes its column (no SpMV).  Working precision ``dtype`` throughout;
+    the basis is stored in ``dtype`` (no bf16 variant: the correction of A v_j
+    uses the Arnoldi relation, which a rounded basis breaks).
+    """
+    dtype = np.dtype(dtype)
+    one = dtype.type(1)
+    zero = dtype.type(0)
+    r = np.asarray(r, dtype=dtype)
+    n = r.shape[0]
+    kmax = m if kmax is None else min(kmax, m)
+    u_ro = unit_roundoff(dtype)
+
+    gamma = norm2(r)
+    V = np.zeros((n, m + 1), dtype=dtype)
+    Hbar = np.zeros((m + 1, m), dtype=dtype)
+    R = np.zeros((m + 1, m), dtype=dtype)
+    cs = np.zeros(m, dtype=dtype)
+    sn = np.zeros(m, dtype=dtype)
+    g = np.zeros(m + 1, dtype=dtype)
+    hist = []
+    if not np.isfinite(gamma):
+        return Cycle(0, V[:, :1], Hbar[:1, :0], np.zeros(0, dtype), float(gamma), hist, g[:1],
+                     False, False, True)
+    if gamma == 0:
+        return Cycle(0, V[:, :1], Hbar[:1, :0], np.zeros(0, dtype), 0.0, hist, g[:1],
+                     True, True, False)
+    V[:, 0] = r / gamma
+    g[0] = gamma
+    # iteration 0: first pass of w = A v_0
+    p = np.asarray(op(V[:, 0]), dtype=dtype)
+    h1 = V[:, :1].T @ p
+    Hbar[:1, 0] = h1
+    u = p - V[:, :1] @ h1
+    k = 0
+    breakdown = stopped = numeric_error = False
+    for j in range(1, kmax + 1):
+        Q = V[:, :j]
+        last = j == kmax
+        p = None if last else np.asarray(op(u), dtype=dtype)
+        # the one reduction of the iteration
+        a = Q.T @ u
+        alpha = np.dot(u, u)
+        if not last:
+            c = Q.T @ p
+            gam = np.dot(u, p)
+        rho = np.sqrt(max(alpha - np.dot(a, a), zero))
+        # column j-1 complete: H[:j, j-1] = h1 + h2 (h2 = a), H[j, j-1] = rho
+        Hbar[:j, j - 1] += a
+        Hbar[j, j - 1] = rho
+        col = Hbar[:j, j - 1]
+        colnorm = np.sqrt(np.dot(col, col) + rho * rho)
+        if not (np.isfinite(rho) and np.isfinite(colnorm)):
+            numeric_error = True
+            k = j - 1
+            break
+        # Givens rotation of column j-1 (as in gmres_cycle)
+        jj = j - 1
+        R[: jj + 2, jj] = Hbar[: jj + 2, jj]
+        for i in range(jj):
+            tt = cs[i] * R[i, jj] + sn[i] * R[i + 1, jj]
+            R[i + 1, jj] = -sn[i] * R[i, jj] + cs[i] * R[i + 1, jj]
+            R[i, jj] = tt
+        rr = dtype.type(np.hypot(R[jj, jj], R[jj + 1, jj]))
+        if rr == 0:
+            cs[jj], sn[jj] = one, zero
+        else:
+            cs[jj], sn[jj] = R[jj, jj] / rr, R[jj + 1, jj] / rr
+        R[jj, jj] = rr
+        R[jj + 1, jj] = 0
+        g[jj + 1] = -sn[jj] * g[jj]
+        g[jj] = cs[jj] * g[jj]
+        hist.append(float(abs(g[jj + 1]) / gamma))
+        k = j
+        if rho <= 100.0 * u_ro * colnorm:
+            breakdown = True
+            break
+        # second pass and normalisation of u_j
+        V[:, j] = (u - Q @ a) / rho
+        if stop_abs is not None and abs(g[jj + 1]) <= stop_abs:
+            stopped = True
+            break
+        if last:
+            break
+        # first pass of w = A v_j from the same reduction
+        t = Hbar[: j + 1, :j] @ a
+        h1 = np.empty(j + 1, dtype=dtype)
+        h1[:j] = (c - t[:j]) / rho
+        h1[j] = ((gam - np.dot(a, c)) / rho - t[j]) / rho
+        Hbar[: j + 1, j] = h1
+        u = p / rho - V[:, : j + 1] @ (t / rho + h1)
+    y = back_substitute(R[:k, :k], g[:k])
+    return Cycle(k, V[:, : k + 1], Hbar[: k + 1, :k], y, float(gamma), hist, g[: k + 1],
+                 breakdown, stopped, numeric_error)
+
+
 def back_substitute(Rk: np.ndarray, gk: np.ndarray) -> np.ndarray:
     """Solve the upper-triangular system ``Rk y = gk`` by back substitution."""
     k = gk.shape[0]
@@ -212,8 +335,11 @@ class Result:
     xs: list  # iterate after each refinement (only if keep_iterates)
 
 
-def gmres(A, b, x0=None, m=50, rtol=1e-10, max_iters=100000, check_mode=0, keep_iterates=False):
-    """Restarted GMRES(m) in fp64, Algorithm 1 with CGS2 (plain double baseline)."""
+def gmres(A, b, x0=None, m=50, rtol=1e-10, max_iters=100000, check_mode=0, keep_iterates=False,
+          ortho="cgs2"):
+    """Restarted GMRES(m) in fp64, Algorithm 1 with CGS2 (plain double baseline).
+
+    ``ortho="dcgs2"``: the one-reduction CGS2 of ``gmres_cycle_lowsync``."""
     M = csr_matrix(A, np.float64)
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64)
@@ -237,8 +363,12 @@ def gmres(A, b, x0=None, m=50, rtol=1e-10, max_iters=100000, check_mode=0, keep_
             res.status = NOT_CONVERGED
             break
         stop = rtol * beta if check_mode == 1 else None
-        cyc = gmres_cycle(lambda v: spmv(M, v), r, m, np.float64, "same",
-                          kmax=min(m, max_iters - res.iters), stop_abs=stop)
+        if ortho == "dcgs2":
+            cyc = gmres_cycle_lowsync(lambda v: spmv(M, v), r, m, np.float64,
+                                      kmax=min(m, max_iters - res.iters), stop_abs=stop)
+        else:
+            cyc = gmres_cycle(lambda v: spmv(M, v), r, m, np.float64, "same",
+                              kmax=min(m, max_iters - res.iters), stop_abs=stop)
         if cyc.numeric_error:
             res.status = ERR_NUMERIC
             break
@@ -297,7 +427,7 @@ def block_jacobi_apply(inverses, v: np.ndarray, dtype) -> np.ndarray:
 
 def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
              max_iters=100000, check_mode=0, poly_roots=None, keep_iterates=False, max_refinements=0,
-             poly_prec=None, bj_block=0):
+             poly_prec=None, bj_block=0, ortho="cgs2"):
     """GMRES-IR (Algorithm 2): fp64 residual and update around an inner GMRES(m).
 
     ``inner`` is ``"fp32"`` or ``"fp64"``; ``basis`` is ``"same"`` or ``"bf16"``
@@ -314,8 +444,12 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
     casts the result back); every other operation stays in fp64.
     ``bj_block > 0``: right block-Jacobi preconditioning instead, the inverses
     of the diagonal blocks computed and applied in the inner precision.
+    ``ortho="dcgs2"``: the inner cycles use the one-reduction CGS2 of
+    ``gmres_cycle_lowsync`` (basis kept in working precision).
     """
     wp = np.float32 if inner == "fp32" else np.float64
+    if ortho == "dcgs2" and basis != "same":
+        raise ValueError("the one-reduction CGS2 keeps the basis in working precision")
     if basis == "bf16" and wp != np.float32:
         raise ValueError("bf16 basis needs an fp32 inner solve")
     M64 = csr_matrix(A, np.float64)
@@ -367,7 +501,10 @@ def gmres_ir(A, b, x0=None, m=50, rtol=1e-10, inner="fp32", basis="same", cap=0,
         used = 0
         numeric = False
         while used < budget:
-            cyc = gmres_cycle(op, rin, m, wp, basis, kmax=min(m, budget - used), stop_abs=stop)
+            if ortho == "dcgs2":
+                cyc = gmres_cycle_lowsync(op, rin, m, wp, kmax=min(m, budget - used), stop_abs=stop)
+            else:
+                cyc = gmres_cycle(op, rin, m, wp, basis, kmax=min(m, budget - used), stop_abs=stop)
             if cyc.numeric_error:
                 numeric = True
                 break
