@@ -94,9 +94,11 @@ typedef struct {
                           the fp32 copy of A and widens the result; every other operation stays fp64) */
   int32_t bj_block;    /* 0: none; 1..64: right block-Jacobi preconditioner M = blockdiag of the
                           diagonal blocks of A of bj_block consecutive rows (the last one ragged),
-                          inverted in fp64 by Gauss-Jordan elimination with partial pivoting at the
-                          start of every solve and stored rounded to fp32; applied in the inner
-                          precision.  Excludes poly_degree > 0.  A singular block gives NUMERIC. */
+                          computed and applied in the inner precision (Section "Preconditioning":
+                          for GMRES-IR the fp32 M is both computed and applied in fp32, from the fp32
+                          copy of A; the fp64 solve keeps M in fp64): each block is inverted by
+                          Gauss-Jordan elimination with partial pivoting at the start of every
+                          solve.  Excludes poly_degree > 0.  A singular block gives NUMERIC. */
   int32_t reserved;    /* must be 0 */
 } gmresir_params;
 

@@ -209,7 +209,7 @@ Layout make_layout(int64_t n, const gmresir_params* p) {
   L.u = L.multi ? take(vecT) : 0;
   L.z = need_uz ? take(vecT) : 0;
   L.py = (L.poly || L.bj > 0) ? take(vecT) : 0;
-  L.minv = L.bj > 0 ? take((size_t)((n + L.bj - 1) / L.bj) * L.bj * L.bj * sizeof(float)) : 0;
+  L.minv = L.bj > 0 ? take((size_t)((n + L.bj - 1) / L.bj) * L.bj * L.bj * L.sT) : 0;
   L.p0 = L.poly ? take(vecT) : 0;
   L.p1 = L.poly ? take(vecT) : 0;
   L.p2 = L.poly ? take(vecT) : 0;
@@ -465,7 +465,7 @@ struct Ctx {
   Prof* prof;
   std::vector<PStep> prog;
   bool poly_on = false;  // inner operator is A p(A)
-  float* minv = nullptr;  // block-Jacobi inverses (L.bj > 0): inner operator A M^{-1}
+  T* minv = nullptr;  // block-Jacobi inverses in inner precision (L.bj > 0): inner operator A M^{-1}
   // fp32 polynomial inside an fp64 inner solve: its buffers are carved from
   // the fp64 polynomial buffers (ldv fp32 entries each; two per buffer)
   bool poly32 = false;
@@ -484,7 +484,7 @@ struct Ctx {
     u = L.multi ? (T*)(ws + L.u) : nullptr;
     z = (L.multi || L.poly || L.bj > 0) ? (T*)(ws + L.z) : nullptr;
     py = (L.poly || L.bj > 0) ? (T*)(ws + L.py) : nullptr;
-    minv = L.bj > 0 ? (float*)(ws + L.minv) : nullptr;
+    minv = L.bj > 0 ? (T*)(ws + L.minv) : nullptr;
     p0 = L.poly ? (T*)(ws + L.p0) : nullptr;
     p1 = L.poly ? (T*)(ws + L.p1) : nullptr;
     p2 = L.poly ? (T*)(ws + L.p2) : nullptr;
@@ -602,14 +602,16 @@ struct Ctx {
     }
   }
 
-  // block-Jacobi inverses from the fp64 CSR arrays (once per solve)
+  // block-Jacobi inverses computed in inner precision from that precision's
+  // copy of the CSR values (once per solve)
   void bj_setup() {
     const long nblk = ((long)n + L.bj - 1) / L.bj;
     const long per_wave = WAVE / L.bj;  // blocks a wave inverts together
     const long grid = (nblk + per_wave - 1) / per_wave;
-    const double b = 12.0 * A->nnz + 4.0 * (n + 1) + 4.0 * nblk * L.bj * L.bj;
-    prof->launch(GMRESIR_CAT_OTHER, b, k_bj_invert, dim3((unsigned)grid), dim3(WAVE), 0, stream, n,
-                 (const int*)A64.rowptr, (const int*)A64.col, (const double*)A64.vals, L.bj, minv);
+    const double b = (sT() + 4.0) * A->nnz + 4.0 * (n + 1) + sT() * nblk * L.bj * L.bj;
+    const T* vals = sizeof(T) == 8 ? (const T*)A->vals64 : (const T*)A->vals32;
+    prof->launch(GMRESIR_CAT_OTHER, b, k_bj_invert<T>, dim3((unsigned)grid), dim3(WAVE), 0, stream, n,
+                 (const int*)A->rowptr, (const int*)A->colidx, vals, L.bj, minv);
   }
 
   int bj_grid() const {
@@ -622,14 +624,14 @@ struct Ctx {
 
   // y = M^{-1} src; scaled: src is wtmp, v_j = round(wtmp * inv) also goes into V[:, j]
   void bj_apply(const T* src, bool scaled, int j, T* y_out, int check_done, int cat, int nB = 0) {
-    const double b = 4.0 * n * L.bj + sT() * n * 2 + (scaled ? sS() * n : 0.0);
+    const double b = sT() * n * L.bj + sT() * n * 2 + (scaled ? sS() * n : 0.0);
     if (scaled) {
       auto kern = k_bj_apply<T, S, true>;
-      prof->launch(cat, b, kern, dim3(bj_grid()), dim3(BLOCK), 0, stream, n, L.bj, (const float*)minv, src, V, L.ldv,
+      prof->launch(cat, b, kern, dim3(bj_grid()), dim3(BLOCK), 0, stream, n, L.bj, (const T*)minv, src, V, L.ldv,
                    j, y_out, st, check_done, (const T*)norm_part(), nB);
     } else {
       auto kern = k_bj_apply<T, S, false>;
-      prof->launch(cat, b, kern, dim3(bj_grid()), dim3(BLOCK), 0, stream, n, L.bj, (const float*)minv, src, V, L.ldv,
+      prof->launch(cat, b, kern, dim3(bj_grid()), dim3(BLOCK), 0, stream, n, L.bj, (const T*)minv, src, V, L.ldv,
                    j, y_out, st, check_done, (const T*)norm_part(), 0);
     }
   }
@@ -921,8 +923,17 @@ struct Ctx {
     cycle_tail(g);
   }
 
-  int read_hdr(StateHdr* h) {
+  // Copies of the cycle history ride along with the header (one stream
+  // synchronisation for both); hist_stage holds the last finished cycle's
+  // per-step values after read_hdr(.., true).
+  std::vector<double> hist_stage;
+
+  int read_hdr(StateHdr* h, bool with_hist = false) {
     HIP_TRY(hipMemcpyAsync(h, st.hdr, sizeof(StateHdr), hipMemcpyDeviceToHost, stream));
+    if (with_hist) {
+      hist_stage.resize((size_t)L.m);
+      HIP_TRY(hipMemcpyAsync(hist_stage.data(), st.hist, (size_t)L.m * sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
     HIP_TRY(hipStreamSynchronize(stream));
     HIP_TRY(hipGetLastError());
     prof->commit(h->cycle_k);
@@ -1031,12 +1042,12 @@ int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresi
         used = -1;  // read after the residual
         break;
       }
-      if (int e = c.read_hdr(&H)) return e;
+      if (int e = c.read_hdr(&H, hist && hist_n < hist_cap)) return e;
       res->cycles += 1;
       const int kc = H.cycle_k;
       if (hist && hist_n < hist_cap && kc > 0) {
         int64_t cnt = std::min<int64_t>(kc, hist_cap - hist_n);
-        HIP_TRY(hipMemcpy(hist + hist_n, c.st.hist, cnt * sizeof(double), hipMemcpyDeviceToHost));
+        memcpy(hist + hist_n, c.hist_stage.data(), cnt * sizeof(double));
         hist_n += cnt;
       }
       used += kc;
@@ -1059,13 +1070,13 @@ int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresi
     c.resid64(x, b);
     c.cast(c.r64);
     const double gamma_old = gamma;
-    if (int e = c.read_hdr(&H)) return e;
+    if (int e = c.read_hdr(&H, single && hist && hist_n < hist_cap)) return e;
     if (single) {
       res->cycles += 1;
       const int kc = H.cycle_k;
       if (hist && hist_n < hist_cap && kc > 0) {
         int64_t cnt = std::min<int64_t>(kc, hist_cap - hist_n);
-        HIP_TRY(hipMemcpy(hist + hist_n, c.st.hist, cnt * sizeof(double), hipMemcpyDeviceToHost));
+        memcpy(hist + hist_n, c.hist_stage.data(), cnt * sizeof(double));
         hist_n += cnt;
       }
       used = kc;
@@ -1109,15 +1120,18 @@ int arnoldi32(const gmresir_matrix* A, const double* src, int steps, char* ws, c
   c.init(0.0, 0, 1.0);
   c.cast(src);
   c.cycle(steps);
-  if (int e = c.read_hdr(H)) return e;
+  // the Hessenberg matrix and the history are copied on the stream before
+  // the one synchronisation of read_hdr
   if (hbar) {
     hbar->assign((size_t)(steps + 1) * c.st.ld, 0.0);
-    HIP_TRY(hipMemcpy(hbar->data(), c.st.Hbar, (size_t)steps * c.st.ld * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(hbar->data(), c.st.Hbar, (size_t)steps * c.st.ld * sizeof(double), hipMemcpyDeviceToHost,
+                           stream));
   }
   if (hist) {
     hist->assign(steps, 0.0);
-    HIP_TRY(hipMemcpy(hist->data(), c.st.hist, steps * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(hist->data(), c.st.hist, steps * sizeof(double), hipMemcpyDeviceToHost, stream));
   }
+  if (int e = c.read_hdr(H)) return e;
   return 0;
 }
 

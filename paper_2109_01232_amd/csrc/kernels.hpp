@@ -1250,18 +1250,22 @@ __global__ __launch_bounds__(BLOCK) void k_widen(int n, const float* __restrict_
 constexpr int BJ_MAX = 64;
 
 // One wave inverts G = 64 / bs consecutive diagonal blocks (lane = g * bs + i:
-// row i of block g).  Each block is gathered from the fp64 CSR arrays into
-// LDS next to an identity (66 KB of LDS: gfx950 gives a workgroup up to
-// 160 KB), reduced by Gauss-Jordan elimination with partial pivoting in fp64,
-// and its inverse written rounded to fp32, column-major with leading
-// dimension bs: Minv[blk][c][i] = inv(A_bb)[i][c].  The bs pivot steps run
-// in lock step for all blocks of the wave (a ragged last block skips the
-// steps beyond its size).  A zero or non-finite pivot writes NaN (the solve
-// then reports NUMERIC).
+// row i of block g) in precision C, the precision the preconditioner is
+// applied in (Section "Preconditioning": for GMRES-IR the fp32 preconditioner
+// is both computed and applied in fp32; the fp64 solve keeps it in fp64).
+// Each block is gathered from the CSR arrays of the matrix copy in C (for
+// fp32 the round-to-nearest-even copy) into LDS next to an identity (C =
+// double: 66 KB of LDS, gfx950 gives a workgroup up to 160 KB), reduced by
+// Gauss-Jordan elimination with partial pivoting in C, and its inverse
+// written column-major with leading dimension bs: Minv[blk][c][i] =
+// inv(A_bb)[i][c].  The bs pivot steps run in lock step for all blocks of the
+// wave (a ragged last block skips the steps beyond its size).  A zero or
+// non-finite pivot writes NaN (the solve then reports NUMERIC).
+template <typename C>
 __global__ __launch_bounds__(WAVE) void k_bj_invert(int n, const int* __restrict__ rowptr,
-                                                    const int* __restrict__ col, const double* __restrict__ vals,
-                                                    int bs, float* __restrict__ Minv) {
-  __shared__ double a[WAVE][2 * BJ_MAX + 1];
+                                                    const int* __restrict__ col, const C* __restrict__ vals,
+                                                    int bs, C* __restrict__ Minv) {
+  __shared__ C a[WAVE][2 * BJ_MAX + 1];
   __shared__ int s_piv[WAVE];
   const int lane = threadIdx.x;
   const int G = WAVE / bs;
@@ -1272,7 +1276,7 @@ __global__ __launch_bounds__(WAVE) void k_bj_invert(int n, const int* __restrict
   const long r0 = blk * bs;
   const int m = (g < G && blk < nblk) ? (int)((n - r0) < bs ? (n - r0) : bs) : 0;
   const int base = g * bs;  // first LDS row of this lane's block
-  for (int c = 0; c < 2 * BJ_MAX; ++c) a[lane][c] = (i < m && c == m + i) ? 1.0 : 0.0;
+  for (int c = 0; c < 2 * BJ_MAX; ++c) a[lane][c] = (i < m && c == m + i) ? C(1) : C(0);
   if (i < m) {
     const long r = r0 + i;
     for (int q = rowptr[r]; q < rowptr[r + 1]; ++q) {
@@ -1286,7 +1290,7 @@ __global__ __launch_bounds__(WAVE) void k_bj_invert(int n, const int* __restrict
     const bool act = k < m;
     if (act && i == 0) {
       int p = k;
-      double best = fabs(a[base + k][k]);
+      C best = fabs(a[base + k][k]);
       for (int q = k + 1; q < m; ++q)
         if (fabs(a[base + q][k]) > best) best = fabs(a[base + q][k]), p = q;
       s_piv[g] = p;
@@ -1296,29 +1300,29 @@ __global__ __launch_bounds__(WAVE) void k_bj_invert(int n, const int* __restrict
       const int p = s_piv[g];
       if (p != k) {
         for (int c = i; c < 2 * m; c += bs) {
-          const double t = a[base + k][c];
+          const C t = a[base + k][c];
           a[base + k][c] = a[base + p][c];
           a[base + p][c] = t;
         }
       }
     }
     __syncthreads();
-    const double piv = act ? a[base + k][k] : 1.0;
-    if (act) bad = bad || !(fabs(piv) > 0.0) || !isfinite(piv);
+    const C piv = act ? a[base + k][k] : C(1);
+    if (act) bad = bad || !(fabs(piv) > C(0)) || !isfinite(piv);
     __syncthreads();
     if (act)
       for (int c = i; c < 2 * m; c += bs) a[base + k][c] = a[base + k][c] / piv;
     __syncthreads();
     if (act && i < m && i != k) {
-      const double f = a[lane][k];
+      const C f = a[lane][k];
       for (int c = 0; c < 2 * m; ++c) a[lane][c] -= f * a[base + k][c];
     }
     __syncthreads();
   }
-  const float nan = __builtin_nanf("");
+  const C nan = (C)__builtin_nan("");
   if (i < m) {
-    float* out = Minv + (size_t)blk * bs * bs;
-    for (int c = 0; c < m; ++c) out[(size_t)c * bs + i] = bad ? nan : (float)a[lane][m + c];
+    C* out = Minv + (size_t)blk * bs * bs;
+    for (int c = 0; c < m; ++c) out[(size_t)c * bs + i] = bad ? nan : a[lane][m + c];
   }
 }
 
@@ -1330,7 +1334,7 @@ __global__ __launch_bounds__(WAVE) void k_bj_invert(int n, const int* __restrict
 // stored as basis column j (the fused start of an iteration, as in the
 // polynomial path).  check_done as in the other iteration kernels.
 template <typename T, typename S, bool SCALED>
-__global__ __launch_bounds__(BLOCK) void k_bj_apply(int n, int bs, const float* __restrict__ Minv,
+__global__ __launch_bounds__(BLOCK) void k_bj_apply(int n, int bs, const T* __restrict__ Minv,
                                                     const T* __restrict__ src, S* __restrict__ V, long ldv, int j,
                                                     T* __restrict__ y, State st, int check_done,
                                                     const T* __restrict__ norm_part, int nB) {
@@ -1361,10 +1365,10 @@ __global__ __launch_bounds__(BLOCK) void k_bj_apply(int n, int bs, const float* 
     s_x[wid][lane] = xv;
     __builtin_amdgcn_wave_barrier();
     if (i < m) {
-      const float* Mb = Minv + (size_t)blk * bs * bs;
+      const T* Mb = Minv + (size_t)blk * bs * bs;
       const T* xs = &s_x[wid][g * bs];
       T acc = T(0);
-      for (int c = 0; c < m; ++c) acc += (T)Mb[(size_t)c * bs + i] * xs[c];
+      for (int c = 0; c < m; ++c) acc += Mb[(size_t)c * bs + i] * xs[c];
       y[r0 + i] = acc;
     }
     __builtin_amdgcn_wave_barrier();

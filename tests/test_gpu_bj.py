@@ -1,12 +1,16 @@
-"""GPU parity of the block-Jacobi preconditioner (right preconditioning in
-the fp32 inner solve of GMRES-IR) through the C ABI, against the oracle.
+"""GPU parity of the block-Jacobi preconditioner (right preconditioning,
+inverses computed and applied in the inner precision: Section
+"Preconditioning", case (b), for GMRES-IR's fp32 inner solve) through the C
+ABI, against the oracle.
 
-Bars: final fp64 relative residual <= 1e-10 on both sides; solutions within
-1e-7 relative; the first cycle's implicit history within 1e-4 (the block
-inverses come from different eliminations -- Gauss-Jordan with partial
-pivoting on the GPU, LAPACK on the host -- and agree after rounding to fp32
-up to an ulp; the block products sum in a different order); iteration counts
-within one restart cycle."""
+Bars, compared at a parity tolerance rtol = 1e-12: final fp64 relative
+residual <= 1e-12 on both sides; solutions within 1e-8 relative; the first
+cycle's implicit history within 1e-5; iteration counts within one restart
+cycle.  The fp32 block inverses come from different eliminations of the same
+fp32 blocks (Gauss-Jordan with partial pivoting on the GPU, LAPACK LU on the
+host) and differ at fp32 rounding level; measured: history gaps 3e-8..1.2e-7,
+solution gaps 9e-14..7e-12, equal iteration counts but for one step at block
+size 32."""
 import numpy as np
 import pytest
 
@@ -36,16 +40,16 @@ def test_bj_solve_matches_oracle(bs):
     M = B.Matrix.from_csr(s.A)
     b = dev_tensor(s.b)
     say("bj solve", bs)
-    x, d, h = B.solve(M, b, restart=50, inner="fp32", rtol=1e-10, check_mode=1, bj_block=bs, hist_cap=100000)
-    ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-10, inner="fp32", bj_block=bs, check_mode=1)
+    x, d, h = B.solve(M, b, restart=50, inner="fp32", rtol=1e-12, check_mode=1, bj_block=bs, hist_cap=100000)
+    ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-12, inner="fp32", bj_block=bs, check_mode=1)
     xs = x.cpu().numpy()
     assert d["status"] == B.OK and ref.status == L.OK
     true = np.linalg.norm(s.b - s.A.scipy() @ xs) / np.linalg.norm(s.b)
-    assert true <= 1e-10 and ref.rel_resid <= 1e-10
-    assert rel(xs, ref.x) <= 1e-7
+    assert true <= 1e-12 and ref.rel_resid <= 1e-12
+    assert rel(xs, ref.x) <= 1e-8
     assert abs(d["iters"] - ref.iters) <= 50
     k1 = ref.cycle_starts[1] if len(ref.cycle_starts) > 1 else len(ref.hist)
-    assert np.max(np.abs(h[:k1] - np.array(ref.hist[:k1]))) <= 1e-4
+    assert np.max(np.abs(h[:k1] - np.array(ref.hist[:k1]))) <= 1e-5
     M.close()
 
 
@@ -54,10 +58,12 @@ def test_bj_fp64_inner_and_arguments():
     M = B.Matrix.from_csr(s.A)
     b = dev_tensor(s.b)
     say("bj fp64 inner")
-    x, d, _ = B.solve(M, b, restart=50, inner="fp64", rtol=1e-10, check_mode=1, bj_block=16)
-    ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-10, inner="fp64", bj_block=16, check_mode=1)
+    x, d, h = B.solve(M, b, restart=50, inner="fp64", rtol=1e-12, check_mode=1, bj_block=16, hist_cap=100000)
+    ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-12, inner="fp64", bj_block=16, check_mode=1)
     assert d["status"] == B.OK and ref.status == L.OK
-    assert rel(x.cpu().numpy(), ref.x) <= 1e-7
+    assert rel(x.cpu().numpy(), ref.x) <= 1e-8
+    assert d["iters"] == ref.iters
+    assert np.max(np.abs(h[:50] - np.array(ref.hist[:50]))) <= 1e-10
     assert B.gmresir_workspace_bytes(M, B.make_params(bj_block=65)) == 0
     assert B.gmresir_workspace_bytes(M, B.make_params(bj_block=8, poly_degree=4)) == 0
     M.close()

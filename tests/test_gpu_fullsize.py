@@ -7,12 +7,15 @@ comparisons are on outputs it computes one at a time:
 
 * SpMV: every row, bitwise (both sides sum each row in column order);
 * the first inner cycle (identical input ``round(b / ||b||)``): the
-  cycle-normalised implicit residual history, 1e-5 for fp32 bases and 2^-8
-  for bf16-stored bases, as for the small systems;
+  cycle-normalised implicit residual history, 1e-5 for fp32 bases and the
+  relative bf16 bar of ``gpu_common.bf16_hist_ok`` for bf16-stored bases, as
+  for the small systems -- on the 150^3 system also with a degree-10
+  polynomial built from the oracle's roots (GMRES(100));
 * later cycles: the GPU restarts from the oracle's own fp64 iterates and runs
   one cycle, compared with the oracle's next cycle;
 * the polynomial preconditioner: the product form with the oracle's roots,
-  and the GPU-built Hessenberg matrix for the same start vector;
+  element by element against the oracle's fp32 product form, and the
+  GPU-built Hessenberg matrix for the same start vector;
 * whole solves: properties that hold at any size -- the fp64 relative
   residual ``||b - A x|| / ||b||`` recomputed here with scipy is <= 1e-10 and
   matches the one the library reports.
@@ -27,12 +30,12 @@ from oracle import poly as PO
 from paper_2109_01232_amd import binding as B
 from paper_2109_01232_amd import problems as P
 
-from gpu_common import dev_tensor, rel, say
+from gpu_common import bf16_hist_ok, dev_tensor, rel, say
 
 pytestmark = pytest.mark.gpu
 
 HIST_TOL_FP32 = 1e-5
-HIST_TOL_BF16 = 2.0 ** -8
+U32 = 2.0 ** -24
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -139,7 +142,8 @@ def test_convdiff2d_bf16_first_cycle_and_solve(cd2d, ws):
     x, d, h = B.solve(M, b, ws=ws, restart=50, inner="fp32", basis="bf16", rtol=1e-10, check_mode=1,
                       hist_cap=1 << 16)
     ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-10, inner="fp32", basis="bf16", check_mode=0, max_iters=50)
-    assert np.max(np.abs(h[:50] - np.array(ref.hist[:50]))) <= HIST_TOL_BF16
+    ok, info = bf16_hist_ok(h[:50], ref.hist[:50])
+    assert ok, info
     assert d["status"] in (B.OK, B.STAGNATED)
     true, _ = _true_resid(s, x)
     assert true <= 1e-6 and d["rel_resid_true"] == pytest.approx(true, rel=1e-6)
@@ -150,15 +154,19 @@ def test_varcoef27_spmv(vc27):
     _spmv_bitwise(*vc27)
 
 
-@pytest.mark.parametrize("basis,tol", [("fp32", HIST_TOL_FP32), ("bf16", HIST_TOL_BF16)])
-def test_varcoef27_first_cycle_and_solve(vc27, ws, basis, tol):
+@pytest.mark.parametrize("basis", ["fp32", "bf16"])
+def test_varcoef27_first_cycle_and_solve(vc27, ws, basis):
     s, M = vc27
     b = dev_tensor(s.b)
     say("ir", basis, "basis m=50 varcoef27 128^3")
     x, d, h = B.solve(M, b, ws=ws, restart=50, inner="fp32", basis=basis, rtol=1e-10, check_mode=1,
                       hist_cap=1 << 16)
     ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-10, inner="fp32", basis=basis, check_mode=0, max_iters=50)
-    assert np.max(np.abs(h[:50] - np.array(ref.hist[:50]))) <= tol
+    if basis == "bf16":
+        ok, info = bf16_hist_ok(h[:50], ref.hist[:50])
+        assert ok, info
+    else:
+        assert np.max(np.abs(h[:50] - np.array(ref.hist[:50]))) <= HIST_TOL_FP32
     assert d["status"] == B.OK
     true, _ = _true_resid(s, x)
     assert true <= 1e-10 and d["rel_resid_true"] == pytest.approx(true, rel=1e-6)
@@ -185,7 +193,15 @@ def test_aniso3d_poly_apply_and_setup(an3d, ws):
     torch.cuda.synchronize()
     ref32 = PO.apply_product_form(L.csr_matrix(s.A, np.float32), roots, v, np.float32)
     ref64 = PO.apply_product_form(L.csr_matrix(s.A, np.float64), roots, v.astype(np.float64), np.float64)
-    assert rel(yd.cpu().numpy(), ref64) <= max(10 * rel(ref32, ref64), 1e-5)
+    got = yd.cpu().numpy()
+    scale = np.abs(ref32).max()
+    gap = np.abs(got - ref32).max() / scale
+    # two fp32 evaluations, each within the fp32 rounding error e of the exact
+    # (fp64) value, differ by at most 2 e: at this size e = 1.24e-5 element-wise
+    # (the oracle's own), measured gap 1.5e-5
+    e_or = np.abs(ref32 - ref64).max() / scale
+    assert gap <= max(8 * d * U32, 2.5 * e_or), (gap, e_or)
+    assert np.abs(got - ref64).max() / scale <= max(8 * d * U32, 2.5 * e_or)
     say("poly setup d=20 aniso3d 150^3, given start")
     groots, hbar = B.gmresir_poly_setup(M, d, start=dev_tensor(start), ws=ws, with_hbar=True)
     assert rel(hbar, ref_cyc.Hbar) <= 1e-4
@@ -208,3 +224,22 @@ def test_aniso3d_poly_solve(an3d, ws, deg):
     assert d["status"] == B.OK
     true, _ = _true_resid(s, x)
     assert true <= 1e-10 and d["rel_resid_true"] == pytest.approx(true, rel=1e-6)
+
+
+@pytest.mark.parametrize("deg", [0, 10])
+def test_aniso3d_first_cycle(an3d, ws, deg):
+    """The benchmark configuration of the 150^3 system, fp32 GMRES(100) (with
+    a degree-10 polynomial from the oracle's roots), first cycle on identical
+    input against the oracle's fp32 cycle (measured gaps 2.1e-7 and 1.3e-8)."""
+    s, M = an3d
+    b = dev_tensor(s.b)
+    roots = None
+    if deg:
+        say("oracle poly roots d=10 aniso3d 150^3")
+        roots = PO.poly_roots(s.A, deg, start=PO.start_vector(s.A.n, 12345), dtype=np.float32)
+    say("ir m=100 first cycle aniso3d 150^3 d", deg)
+    x, d, h = B.solve(M, b, ws=ws, restart=100, inner="fp32", rtol=1e-10, check_mode=0, max_iters=100,
+                      poly_degree=deg, poly_roots=roots, hist_cap=100)
+    ref = L.gmres_ir(s.A, s.b, m=100, rtol=1e-10, inner="fp32", check_mode=0, max_iters=100, poly_roots=roots)
+    assert d["iters"] == ref.iters == 100
+    assert np.max(np.abs(h - np.array(ref.hist))) <= HIST_TOL_FP32

@@ -2,11 +2,17 @@
 
 Bars: bitwise for the fp32/fp64 SpMV on stencil rows (both sum each row in
 column order from identically rounded products); final fp64 relative
-residual <= rtol for both sides; solution agreement 1e-8 relative (the
-parity system has condition number ~1e3, so two solutions with residual
-1e-12 agree to ~1e-9); cycle-normalised implicit residual histories within
-1e-5 for fp32 cycles (the measured fp32-vs-fp64 gap on these systems is
-~2e-7) and within 2^-8 for bf16-stored bases (bf16 unit step).
+residual <= rtol for both sides; solution agreement 1e-8 relative, compared
+at a parity tolerance rtol = 1e-12 (the parity system has condition number
+~1e3, so two solutions with residual 1e-12 agree to ~1e-9; measured GPU-oracle
+gaps 1e-16..7e-12); cycle-normalised implicit residual histories within 1e-5
+for fp32 cycles (measured gaps up to 2e-7); for bf16-stored bases a relative
+bar on every step, |d rho_j| <= BF16_REL rho_j + BF16_FLOOR (see
+``bf16_hist_ok``); the fp32 polynomial apply element by element against the
+oracle's fp32 product form, max |dy| <= max(8 d u32, 2.5 e) max |y| with e the
+oracle's own element-wise fp32 error against the fp64 evaluation (two fp32
+evaluations of d product-form steps each within e of the exact value;
+measured 1.7e-7 at d = 1 .. 6.1e-6 at d = 40).
 """
 import numpy as np
 import pytest
@@ -18,12 +24,12 @@ from oracle import poly as PO
 from paper_2109_01232_amd import binding as B
 from paper_2109_01232_amd import problems as P
 
-from gpu_common import cycle_slices, dev_tensor, rel, say
+from gpu_common import bf16_hist_ok, cycle_slices, dev_tensor, rel, say
 
 pytestmark = pytest.mark.gpu
 
 HIST_TOL_FP32 = 1e-5
-HIST_TOL_BF16 = 2.0 ** -8
+U32 = 2.0 ** -24
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -218,7 +224,8 @@ def test_bf16_basis(cfg1):
     x, d, h = B.solve(M, b, restart=50, inner="fp32", basis="bf16", rtol=1e-10, check_mode=0, hist_cap=100000)
     ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-10, inner="fp32", basis="bf16", check_mode=0)
     assert d["status"] == B.OK and d["rel_resid_true"] <= 1e-10
-    assert np.max(np.abs(h[:50] - np.array(ref.hist[:50]))) <= HIST_TOL_BF16
+    ok, info = bf16_hist_ok(h[:50], ref.hist[:50])
+    assert ok, info
     assert abs(d["refinements"] - ref.refinements) <= 2
     assert rel(x.cpu().numpy(), s.u) <= 1e-6
 
@@ -287,14 +294,14 @@ def test_restart_lengths_and_fallbacks(m):
     for inner in ("fp64", "fp32"):
         say("restart", m, inner)
         maxit = 4000 if m > 1 else 20000
-        x, d, h = B.solve(M, b, restart=m, inner=inner, rtol=1e-10, max_iters=maxit, check_mode=1,
+        x, d, h = B.solve(M, b, restart=m, inner=inner, rtol=1e-12, max_iters=maxit, check_mode=1,
                           hist_cap=200)
-        ref = (L.gmres(A, bb, m=m, rtol=1e-10, max_iters=maxit, check_mode=1) if inner == "fp64" else
-               L.gmres_ir(A, bb, m=m, rtol=1e-10, inner="fp32", max_iters=maxit, check_mode=1))
+        ref = (L.gmres(A, bb, m=m, rtol=1e-12, max_iters=maxit, check_mode=1) if inner == "fp64" else
+               L.gmres_ir(A, bb, m=m, rtol=1e-12, inner="fp32", max_iters=maxit, check_mode=1))
         assert d["status"] == ref.status
         if d["status"] == B.OK:
-            assert d["rel_resid_true"] <= 1e-10
-            assert rel(x.cpu().numpy(), ref.x) <= 1e-7
+            assert d["rel_resid_true"] <= 1e-12
+            assert rel(x.cpu().numpy(), ref.x) <= 1e-8
         # first cycle only: after an implicit early exit the next cycle's input is
         # the rounding noise of the correction, which differs between the sides
         k = min(len(h), ref.cycle_starts[1] if len(ref.cycle_starts) > 1 else len(ref.hist), m)
@@ -322,9 +329,13 @@ def test_ragged_rows_every_basis_width(m, inner, basis):
         tol = 1e-10
     else:
         ref = L.gmres_ir(A, bb, m=m, rtol=1e-10, inner="fp32", basis=basis, check_mode=0, max_iters=m)
-        tol = HIST_TOL_FP32 if basis == "fp32" else HIST_TOL_BF16
+        tol = HIST_TOL_FP32
     k = min(m, len(ref.hist))
-    assert np.max(np.abs(h[:k] - np.array(ref.hist[:k]))) <= tol
+    if basis == "bf16":
+        ok, info = bf16_hist_ok(h[:k], ref.hist[:k])
+        assert ok, info
+    else:
+        assert np.max(np.abs(h[:k] - np.array(ref.hist[:k]))) <= tol
     assert d["status"] == B.OK and d["rel_resid_true"] <= 1e-10
     assert np.linalg.norm(bb - A.scipy() @ x.cpu().numpy()) / np.linalg.norm(bb) <= 1e-10
 
@@ -448,7 +459,7 @@ def aniso_small(n=14, seed=0):
     return A, A.scipy() @ u
 
 
-@pytest.mark.parametrize("d", [1, 2, 5, 10, 20])
+@pytest.mark.parametrize("d", [1, 2, 5, 10, 20, 40])
 def test_poly_apply_matches_oracle(d):
     """Same roots on both sides (drawn from the oracle), fp32 product form."""
     A, _ = aniso_small()
@@ -463,10 +474,14 @@ def test_poly_apply_matches_oracle(d):
     ref = PO.apply_product_form(L.csr_matrix(A, np.float32), roots, v, np.float32)
     ref64 = PO.apply_product_form(L.csr_matrix(A, np.float64), roots, v.astype(np.float64), np.float64)
     got = yd.cpu().numpy()
-    # both fp32 evaluations sit within fp32 rounding of the fp64 value
-    e_ours = rel(got, ref64)
-    e_oracle = rel(ref, ref64)
-    assert e_ours <= max(10 * e_oracle, 1e-5)
+    # element by element against the oracle's fp32 evaluation of the same
+    # roots: two fp32 evaluations, each within the fp32 rounding error e of the
+    # exact (fp64) value, differ by at most 2 e
+    scale = np.abs(ref).max()
+    gap = np.abs(got - ref).max() / scale
+    e_or = np.abs(ref - ref64).max() / scale
+    assert gap <= max(8 * d * U32, 2.5 * e_or), (gap, e_or)
+    assert np.abs(got - ref64).max() / scale <= max(8 * d * U32, 2.5 * e_or)
 
 
 def test_poly_setup_matches_oracle():
@@ -504,9 +519,15 @@ def test_poly_preconditioned_solve():
     assert d1["iters"] < d0["iters"]
     true = np.linalg.norm(bb - A.scipy() @ x1.cpu().numpy()) / np.linalg.norm(bb)
     assert true <= 1e-10
-    ref = L.gmres_ir(A, bb, m=30, rtol=1e-10, inner="fp32", poly_roots=roots, check_mode=1)
-    assert ref.status == L.OK
-    assert abs(d1["iters"] - ref.iters) <= 5
-    k1 = ref.cycle_starts[1] if len(ref.cycle_starts) > 1 else len(ref.hist)
-    assert np.max(np.abs(h1[:k1] - np.array(ref.hist[:k1]))) <= 1e-4
-    assert rel(x1.cpu().numpy(), ref.x) <= 1e-7
+    # parity at rtol 1e-12 (measured: history gap 8e-9, solution gap 9e-12, same iteration count)
+    for deg in (5, 10, 20):
+        roots = PO.poly_roots(A, deg, start=PO.start_vector(A.n, 3), dtype=np.float32)
+        say("poly solve parity d", deg)
+        x2, d2, h2 = B.solve(M, b, restart=30, inner="fp32", rtol=1e-12, poly_degree=deg, poly_roots=roots,
+                             hist_cap=5000)
+        ref = L.gmres_ir(A, bb, m=30, rtol=1e-12, inner="fp32", poly_roots=roots, check_mode=1)
+        assert ref.status == L.OK and d2["status"] == B.OK and d2["rel_resid_true"] <= 1e-12
+        assert abs(d2["iters"] - ref.iters) <= 2
+        k1 = ref.cycle_starts[1] if len(ref.cycle_starts) > 1 else len(ref.hist)
+        assert np.max(np.abs(h2[:k1] - np.array(ref.hist[:k1]))) <= HIST_TOL_FP32
+        assert rel(x2.cpu().numpy(), ref.x) <= 1e-8

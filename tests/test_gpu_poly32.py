@@ -1,14 +1,15 @@
 """GPU parity of fp64 GMRES(m) with an fp32 polynomial preconditioner
 (Section "Preconditioning": an fp32 M applied to fp64 vectors), through the
 C ABI, against the oracle's same mode.  Roots come from the oracle and are
-passed to both sides.  Bars: final fp64 relative residual <= 1e-10 on both
-sides; solutions within 1e-7 relative (condition number ~1e2, residuals
-1e-10); the first cycle's implicit history within 1e-4 (the fp32 polynomial
-is evaluated as fused product-form steps on the GPU, step by step in the
-oracle: rounding differs at the fp32 level, as in the fp32 polynomial
-parity test); and the paper's observation on both sides -- the first cycle's
-implicit residual meets the target while the explicit residual of its
-iterate stays above 1e-8, so restarts are needed."""
+passed to both sides.  Bars, at a parity tolerance rtol = 1e-12: final fp64
+relative residual <= 1e-12 on both sides; solutions within 1e-8 relative; the
+first cycle's implicit history within 1e-5 (the fp32 polynomial is evaluated
+as fused product-form steps on the GPU, step by step in the oracle: rounding
+differs at the fp32 level; measured history gaps 1.2e-8 (d = 10) and 1.6e-7
+(d = 40), solution gaps 3e-12 and 3e-16).  And the paper's observation on both
+sides, at rtol = 1e-10: the first cycle's implicit residual meets the target
+while the explicit residual of its iterate stays above 1e-8, so restarts are
+needed."""
 import numpy as np
 import pytest
 
@@ -46,21 +47,26 @@ def test_fp32_poly_in_fp64_gmres_matches_oracle(d):
     M = B.Matrix.from_csr(A)
     b = dev_tensor(bnp)
     say("fp64 gmres + fp32 poly", d)
-    x, dres, h = B.solve(M, b, restart=50, inner="fp64", rtol=1e-10, check_mode=1, poly_degree=d,
+    x, dres, h = B.solve(M, b, restart=50, inner="fp64", rtol=1e-12, check_mode=1, poly_degree=d,
                          poly_prec="fp32", poly_roots=roots, hist_cap=10000)
-    ref = L.gmres_ir(A, bnp, m=50, rtol=1e-10, inner="fp64", poly_roots=roots, poly_prec="fp32", check_mode=1)
+    ref = L.gmres_ir(A, bnp, m=50, rtol=1e-12, inner="fp64", poly_roots=roots, poly_prec="fp32", check_mode=1)
     xs = x.cpu().numpy()
     assert dres["status"] == B.OK and ref.status == L.OK
     true = np.linalg.norm(bnp - A.scipy() @ xs) / np.linalg.norm(bnp)
-    assert true <= 1e-10 and ref.rel_resid <= 1e-10
-    assert rel(xs, ref.x) <= 1e-7
+    assert true <= 1e-12 and ref.rel_resid <= 1e-12
+    assert rel(xs, ref.x) <= 1e-8
+    assert dres["iters"] == ref.iters
     assert dres["refinements"] >= 2
+    say("fp64 gmres + fp32 poly at 1e-10", d)
+    x, dres, h = B.solve(M, b, restart=50, inner="fp64", rtol=1e-10, check_mode=1, poly_degree=d,
+                         poly_prec="fp32", poly_roots=roots, hist_cap=10000)
+    ref = L.gmres_ir(A, bnp, m=50, rtol=1e-10, inner="fp64", poly_roots=roots, poly_prec="fp32", check_mode=1)
     # first cycle: ends where the implicit residual first meets the target
     k1 = int(np.argmax(h <= 1e-10)) + 1
     assert h[k1 - 1] <= 1e-10
     href = np.array(ref.hist[: ref.cycle_starts[1]])
     n1 = min(k1, len(href))
-    assert np.max(np.abs(h[:n1] - href[:n1])) <= 1e-4
+    assert np.max(np.abs(h[:n1] - href[:n1])) <= 1e-5
     # the same first cycle alone: its explicit residual stays far above the target
     say("fp64 gmres + fp32 poly, first cycle", d, k1)
     x1, d1, _ = B.solve(M, b, restart=50, inner="fp64", rtol=1e-10, check_mode=1, poly_degree=d,
