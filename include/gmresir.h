@@ -174,6 +174,26 @@ int gmresir_solve(const gmresir_matrix* A, const double* b, double* x, const gmr
                   const double* poly_roots_host, void* ws, size_t ws_bytes, gmresir_result* res_host,
                   double* hist_host, int64_t hist_cap, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the same
+   solve as gmresir_solve, with its workspace taken from a static device
+   array of GMRESIR_NOALLOC_MAX_BYTES bytes that the library holds on every
+   GPU it runs on until the process ends.  The call allocates nothing (no
+   hipMalloc / hipFree; no HIP graph is recorded: every kernel is launched
+   directly).  Arguments as for gmresir_solve without ws / ws_bytes.  The
+   device current at the call must be the matrix's device.  Errors as for
+   gmresir_solve, plus WORKSPACE when gmresir_workspace_bytes(A, p) exceeds
+   GMRESIR_NOALLOC_MAX_BYTES (nothing is enqueued), and INVALID_ARG for
+   profile = 1 (per-kernel timing creates HIP events).  Every call on a GPU
+   shares that GPU's array, which keeps the last call's contents (nothing in
+   it needs to start at zero: every solve initialises its state first); calls
+   that overlap in time on one GPU -- on different streams or threads -- race
+   on it and must not be issued. */
+#define GMRESIR_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int gmresir_solve_noalloc(const gmresir_matrix* A, const double* b, double* x, const gmresir_params* p,
+                          const double* poly_roots_host, gmresir_result* res_host, double* hist_host,
+                          int64_t hist_cap, void* stream);
+
 /* ---- GMRES-FD (Section "Mixed Precision GMRES-FD") ---------------------- */
 
 /* Workspace bytes of gmresir_solve_fd (0 if the arguments are invalid). */

@@ -89,6 +89,8 @@ _SIGS = {
     "gmresir_workspace_bytes": (_sz, [_vp, ctypes.POINTER(Params)]),
     "gmresir_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(Params), _dp, _vp, _sz,
                                      ctypes.POINTER(Result), _dp, _i64, _vp]),
+    "gmresir_solve_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(Params), _dp, ctypes.POINTER(Result),
+                                             _dp, _i64, _vp]),
     "gmresir_fd_workspace_bytes": (_sz, [_vp, ctypes.POINTER(Params), _i64]),
     "gmresir_solve_fd": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(Params), _i64, _vp, _sz,
                                         ctypes.POINTER(Result), _dp, _i64, _vp]),
@@ -315,6 +317,26 @@ def gmresir_solve(A: Matrix, b, x, p: Params, poly_roots=None, ws=None, hist_cap
     d = res.as_dict()
     n_hist = min(hist_cap, d["iters"])
     return st, d, hist[:n_hist]
+
+
+# GMRESIR_NOALLOC_MAX_BYTES of the header: the static scratch array's size
+NOALLOC_MAX_BYTES = 64 << 20
+
+
+def gmresir_solve_noalloc(A: Matrix, b, x, p: Params, poly_roots=None, hist_cap=0):
+    """Run gmresir_solve_noalloc (workspace from the library's static device
+    array, nothing allocated); x is updated in place.  Returns (status, result
+    dict, history numpy array); raises GmresirError on negative statuses."""
+    res = Result()
+    hist = np.zeros(max(hist_cap, 0))
+    roots = None if poly_roots is None else roots_to_array(poly_roots)
+    st = lib().gmresir_solve_noalloc(A.handle, _ptr(b), _ptr(x), ctypes.byref(p),
+                                     roots.ctypes.data_as(_dp) if roots is not None else None, ctypes.byref(res),
+                                     hist.ctypes.data_as(_dp) if hist_cap > 0 else None, hist_cap, _stream())
+    if st < 0:
+        raise GmresirError("gmresir_solve_noalloc", st)
+    d = res.as_dict()
+    return st, d, hist[: min(hist_cap, d["iters"])]
 
 
 def solve(A: Matrix, b, x0=None, ws=None, hist_cap=0, poly_roots=None, **kw):

@@ -949,12 +949,12 @@ struct Ctx {
 template <typename T, typename S>
 int solve_impl(const gmresir_matrix* A, const double* b, double* x, const gmresir_params* p,
                const double* roots, char* ws, const Layout& L, gmresir_result* res, double* hist, int64_t hist_cap,
-               hipStream_t stream, int max_refinements = 0) {
+               hipStream_t stream, int max_refinements = 0, bool allow_graph = true) {
   Prof prof;
   prof.on = p->profile == 1;
   prof.stream = stream;
   Ctx<T, S> c(A, ws, L, stream, &prof);
-  c.graph_ok = !prof.on && A->n <= GRAPH_MAX_N;
+  c.graph_ok = allow_graph && !prof.on && A->n <= GRAPH_MAX_N;
   if (L.poly) {
     const char* why = "";
     if (!build_poly_program(p->poly_degree + 1, roots, c.prog, &why)) {
@@ -1192,6 +1192,41 @@ void add_result(gmresir_result* acc, const gmresir_result& r) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// scratch memory of gmresir_solve_noalloc: a file-scope device array; every
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel (in host code it is a
+// host-side stand-in): it looks the device address up once per device.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[GMRESIR_NOALLOC_MAX_BYTES];
+
+namespace {
+
+// Device address of the current device's copy of `scratch` (dev must be the
+// current device), looked up on the first call per device and kept.
+int scratch_ptr(int dev, char** out) {
+  static std::mutex mu;
+  static std::map<int, char*> addr;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) {
+    *out = it->second;
+    return GMRESIR_OK;
+  }
+  void* ptr = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr || ((uintptr_t)ptr) % ALIGN) {
+    set_error("scratch array of device %d is not 256-byte aligned", dev);
+    return GMRESIR_ERR_HIP;
+  }
+  addr[dev] = (char*)ptr;
+  *out = (char*)ptr;
+  return GMRESIR_OK;
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1421,6 +1456,60 @@ int gmresir_solve(const gmresir_matrix* A, const double* b, double* x, const gmr
     st = solve_impl<float, float>(A, b, x, p, poly_roots, (char*)ws, L, res, hist, hist_cap, s);
   else
     st = solve_impl<float, bf16_t>(A, b, x, p, poly_roots, (char*)ws, L, res, hist, hist_cap, s);
+  res->status = st;
+  res->solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+int gmresir_solve_noalloc(const gmresir_matrix* A, const double* b, double* x, const gmresir_params* p,
+                          const double* poly_roots, gmresir_result* res, double* hist, int64_t hist_cap,
+                          void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  const char* why = "";
+  if (!A || !b || !x || !res) {
+    set_error("gmresir_solve_noalloc: NULL argument");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (!valid_params(p, &why)) {
+    set_error("gmresir_solve_noalloc: %s", why);
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (p->profile != 0) {
+    set_error("gmresir_solve_noalloc: profile must be 0 (per-kernel timing creates HIP events)");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (p->poly_degree > 0 && !poly_roots) {
+    set_error("gmresir_solve_noalloc: poly_degree > 0 needs poly_roots_host");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  if (hist_cap < 0 || (hist_cap > 0 && !hist)) {
+    set_error("gmresir_solve_noalloc: bad history buffer");
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != A->device) {
+    set_error("gmresir_solve_noalloc: device %d is current, the matrix lives on device %d", dev, A->device);
+    return GMRESIR_ERR_INVALID_ARG;
+  }
+  const Layout L = make_layout(A->n, p);
+  if (L.total > GMRESIR_NOALLOC_MAX_BYTES) {
+    set_error("gmresir_solve_noalloc: this solve needs %zu bytes of scratch, the static array holds %zu", L.total,
+              (size_t)GMRESIR_NOALLOC_MAX_BYTES);
+    return GMRESIR_ERR_WORKSPACE;
+  }
+  char* ws = nullptr;
+  if (int e = scratch_ptr(dev, &ws)) return e;
+  memset(res, 0, sizeof(*res));
+  hipStream_t s = (hipStream_t)stream;
+  int st;
+  // direct launches only: recording a HIP graph would allocate
+  if (p->inner_prec == GMRESIR_FP64)
+    st = solve_impl<double, double>(A, b, x, p, poly_roots, ws, L, res, hist, hist_cap, s, 0, false);
+  else if (p->basis_prec == GMRESIR_FP32)
+    st = solve_impl<float, float>(A, b, x, p, poly_roots, ws, L, res, hist, hist_cap, s, 0, false);
+  else
+    st = solve_impl<float, bf16_t>(A, b, x, p, poly_roots, ws, L, res, hist, hist_cap, s, 0, false);
   res->status = st;
   res->solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return st;
