@@ -1,17 +1,27 @@
 #!/usr/bin/env python3
 """Time-to-1e-10 of GMRES-IR (fp32 inner GMRES(50), fp64 refinement) on one MI355X.
 
-Workload: 2D convection-diffusion, 5-point centred differences on a
-1000 x 1000 grid (N = 1e6, 4,996,000 nonzeros), Peclet number drawn from
-U[1, 100] with seed 0, wind (1, 1), b = A u with u ~ U[-1, 1], x0 = 0,
-relative residual tolerance 1e-10.  One step = one complete solve (fp64
+Workload (the configuration the comparison of an fp32- and a bf16-stored
+Krylov basis against fp64 GMRES is quoted on): the 27-point variable-
+coefficient nonsymmetric stencil on a 128^3 grid (N = 2,097,152, 55,742,968
+nonzeros; off-diagonals -(1 + 0.3 U[-1,1]) per entry with a skew part of
+scale 0.5, row sums 0.05), seed 0, b = A u with u ~ U[-1, 1], x0 = 0, relative
+residual tolerance 1e-10, restart m = 50.  One step = one complete solve (fp64
 residual, cast, inner cycles of SpMV + CGS2 + Givens, fp64 correction, until
-||b - A x|| / ||b|| <= 1e-10).  fp64 GMRES(50) on the same GPU and system is
-timed beside it.  Inputs are resident in HBM before the timed region.
+||b - A x|| / ||b|| <= 1e-10).  `value` is the fp32-basis GMRES-IR time; the
+bf16-basis GMRES-IR, fp64 GMRES(50) and the learned-parameter variant on the
+same GPU and system are timed beside it, and the 2D 1000^2 and 3D 150^3
+systems once each as extra keys.  Inputs are resident in HBM before the timed
+region.
 
-Prints one JSON line (see the keys below).  Options for profiling runs:
---no-cpu-baseline, --no-fp64, --no-profile, --copy-calibration (a plain
-device copy of known size, for scaling the HBM traffic counters).
+The CPU oracle solves the same system whole (fp32 GMRES-IR and fp64 GMRES)
+on the host's cores: its time is `cpu_baseline` and its solution gives the
+fp64 error ||x - x_oracle|| / ||x_oracle|| of every GPU result.
+
+Prints one JSON line.  Options for profiling runs: --no-cpu-baseline,
+--no-extras, --no-profile, --copy-calibration (a plain device copy of known
+size, for scaling the HBM traffic counters), --only fp32|bf16|fp64 (the
+timed solves of one variant only).
 """
 
 import argparse
@@ -26,13 +36,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "time-to-1e-10 residual (s), GMRES-IR FP32/BF16 vs FP64 GMRES; SpMV+CGS2 HBM GB/s"
+WORKLOAD = "varcoef27_128^3_27pt_seed0"
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_convdiff2d_1000.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_varcoef27_128.json")
 
 
 def kernel_source_hash():
@@ -49,8 +60,9 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed hardware-counter
-    summary, or None when the sources changed since the counters were taken."""
+    """HBM bytes per launch of `kernel` (a profile category) from the committed
+    hardware-counter summary, or None when the sources changed since the
+    counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -62,68 +74,58 @@ def measured_traffic(kernel):
     return None if k is None else k["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(system, gpu_iters, budget_s=20.0):
-    """The CPU oracle on a bounded sample of the same solve, extrapolated per iteration."""
-    import numpy as np
-
-    from oracle import linalg as L
-
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
 
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        threads = os.cpu_count() or 1
-    iters = 0
+        return os.cpu_count() or 1
+
+
+def cpu_oracle(system):
+    """The CPU oracle's whole solves of the workload: fp32 GMRES-IR (the GPU
+    headline's method) and fp64 GMRES(50), each to 1e-10, timed on the host."""
+    from oracle import linalg as L
+
     t0 = time.perf_counter()
-    sample_iters = 100
-    while True:
-        r = L.gmres_ir(system.A, system.b, m=50, rtol=1e-10, inner="fp32", max_iters=sample_iters, check_mode=1)
-        iters = r.iters
-        el = time.perf_counter() - t0
-        if el > 5.0 or sample_iters >= 400:
-            break
-        sample_iters *= 2
-        t0 = time.perf_counter()
-    per_iter = el / max(iters, 1)
-    return {
-        "value": per_iter * gpu_iters,
-        "unit": "s",
-        "cores": int(threads),
-        "kind": "oracle",
-        "sample": f"{iters} inner iterations ({iters // 50} restart cycles) of the oracle's GMRES-IR(50) fp32 on "
-                  f"the same 1000x1000 system in {el:.1f} s, extrapolated to the GPU run's {gpu_iters} iterations",
-        "per_iter_s": per_iter,
-        "cpu": platform.processor() or platform.machine(),
-    }
+    ir = L.gmres_ir(system.A, system.b, m=50, rtol=1e-10, inner="fp32", check_mode=1)
+    t_ir = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    d64 = L.gmres(system.A, system.b, m=50, rtol=1e-10, check_mode=1)
+    t_64 = time.perf_counter() - t0
+    return ir, t_ir, d64, t_64
+
+
+def rel_err(a, b):
+    import numpy as np
+
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--n", type=int, default=1000)
     ap.add_argument("--restart", type=int, default=50)
-    ap.add_argument("--basis", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--only", default=None, choices=["fp32", "bf16", "fp64", "dcgs2"],
+                    help="time only this variant's solves (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-parameter variant")
-    ap.add_argument("--no-fd", action="store_true", help="skip the GMRES-FD switch-point sweep")
-    ap.add_argument("--fd-switch", default="500,1000,2000",
-                    help="GMRES-FD switch points (fp32 iterations before fp64 GMRES takes over)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 2D 1000^2 and 3D 150^3 solves")
     ap.add_argument("--spmv-study", action="store_true",
                     help="only time fp64 vs fp32 SpMV over the stencil families (1000 calls, min of 3), "
                          "one JSON line per family")
-    ap.add_argument("--no-bj", action="store_true", help="skip the block-Jacobi variants")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--max-iters", type=int, default=1_000_000,
                     help="cap on inner iterations of the timed solves (short hardware-counter runs only)")
     ap.add_argument("--suite", action="store_true",
-                    help="also time the other workloads (150^3 anisotropic + polynomial, 128^3 27-point "
-                         "bf16/fp32/fp64, 64^2 parity system); one JSON line each, after the main line")
+                    help="also time the other workloads and variants (GMRES-FD switch points, block Jacobi, "
+                         "polynomial degrees, 3D Laplacian studies, fp32 polynomial in fp64 GMRES); one JSON "
+                         "line each, after the main line")
     ap.add_argument("--suite-only", action="store_true")
     ap.add_argument("--suite-case", default=None,
                     help="run only the suite solves whose 'name/inner/basis/restart/degree' label contains this "
@@ -166,36 +168,60 @@ def main():
         print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 5}), flush=True)
         return
 
-    log("building system")
-    system = P.convdiff2d_system(args.seed, n=args.n)
+    log("building the 27-point 128^3 system")
+    system = P.varcoef27_system(args.seed)
     A = system.A
     M = B.Matrix.from_csr(A)
     b = torch.from_numpy(system.b).cuda()
     x = torch.zeros_like(b)
     ws = B.Workspace()
-    p_ir = B.make_params(restart=args.restart, inner="fp32", basis=args.basis, rtol=1e-10, check_mode=1,
-                         max_iters=args.max_iters)
-    p_64 = B.make_params(restart=args.restart, inner="fp64", rtol=1e-10, check_mode=1)
+    Asp = A.scipy()
+    bnorm = float(np.linalg.norm(system.b))
+    m = args.restart
 
-    def run(p):
-        x.zero_()
-        st, d, _ = B.gmresir_solve(M, b, x, p, ws=ws)
-        return d
+    def timed(p, steps, warmup, roots=None):
+        """mean wall time of `steps` solves (after `warmup`), inputs resident;
+        returns (seconds, result dict, status, solution on the host)."""
+        for _ in range(warmup):
+            x.zero_()
+            B.gmresir_solve(M, b, x, p, poly_roots=roots, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            st, d, _ = B.gmresir_solve(M, b, x, p, poly_roots=roots, ws=ws)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / max(steps, 1)
+        return t, d, st, x.cpu().numpy()
 
-    for _ in range(args.warmup):
-        run(p_ir)
-    torch.cuda.synchronize()
-    log("timed GMRES-IR steps", args.steps)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        d_ir = run(p_ir)
-    torch.cuda.synchronize()
-    t_ir = (time.perf_counter() - t0) / args.steps
-    xs = x.cpu().numpy()
-    sol_err = float(np.linalg.norm(xs - system.u) / np.linalg.norm(system.u))
-    true_resid = float(np.linalg.norm(system.b - A.scipy() @ xs) / np.linalg.norm(system.b))
-    log(f"IR: {t_ir:.4f} s/solve iters={d_ir['iters']} resid={true_resid:.3e}")
+    def describe(t, d, st, xs):
+        true = float(np.linalg.norm(system.b - Asp @ xs) / bnorm)
+        return {"s": t, "iters": d["iters"], "refinements": d["refinements"], "status": B.status_string(st),
+                "rel_resid_true": true, "converged": bool(true <= 1e-10), "sol_err_vs_u": rel_err(xs, system.u)}
 
+    variants = {
+        "fp32": B.make_params(restart=m, inner="fp32", basis="fp32", rtol=1e-10, check_mode=1,
+                              max_iters=args.max_iters),
+        "bf16": B.make_params(restart=m, inner="fp32", basis="bf16", rtol=1e-10, check_mode=1,
+                              max_iters=args.max_iters),
+        "fp64": B.make_params(restart=m, inner="fp64", rtol=1e-10, check_mode=1, max_iters=args.max_iters),
+        # the same fp32 GMRES-IR with the one-reduction CGS2 (second pass delayed one iteration)
+        "dcgs2": B.make_params(restart=m, inner="fp32", basis="fp32", rtol=1e-10, check_mode=1,
+                               max_iters=args.max_iters, ortho="dcgs2"),
+    }
+    results, sols = {}, {}
+    for name, p in variants.items():
+        if args.only and name != args.only:
+            continue
+        steps = args.steps
+        log(f"timed {name} solves: {steps} (warm-up {args.warmup})")
+        t, d, st, xs = timed(p, steps, args.warmup)
+        results[name] = describe(t, d, st, xs)
+        sols[name] = xs
+        log(f"{name}: {t:.4f} s/solve iters={d['iters']} resid={results[name]['rel_resid_true']:.3e}")
+
+    head = results.get("fp32") or next(iter(results.values()))
+    t_ir = head["s"]
     out = {
         "metric": METRIC,
         "value": t_ir,
@@ -210,172 +236,219 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"convdiff2d_{args.n}x{args.n}_5pt_seed{args.seed}",
-            "N": A.n, "nnz": A.nnz, "Pe": system.meta["Pe"], "restart": args.restart,
-            "rtol": 1e-10, "inner": "fp32", "basis": args.basis, "check_mode": 1,
+            "workload": WORKLOAD if args.seed == 0 else f"varcoef27_128^3_27pt_seed{args.seed}",
+            "N": A.n, "nnz": A.nnz, "restart": m, "rtol": 1e-10, "inner": "fp32", "basis": "fp32",
+            "check_mode": 1, "x0": "zero", "rhs": "b = A u, u ~ U[-1,1]",
         },
-        "iters": d_ir["iters"],
-        "refinements": d_ir["refinements"],
-        "status": B.status_string(d_ir["status"]),
-        "converged": bool(true_resid <= 1e-10),
-        "rel_resid_true": true_resid,
-        "sol_err_vs_u": sol_err,
+        "iters": head["iters"],
+        "refinements": head["refinements"],
+        "status": head["status"],
+        "converged": head["converged"],
+        "rel_resid_true": head["rel_resid_true"],
+        "sol_err_vs_u": head["sol_err_vs_u"],
     }
+    if "bf16" in results:
+        out["bf16_basis"] = results["bf16"]
+    if "fp64" in results:
+        out["fp64_gmres"] = results["fp64"]
+        out["fp64_gmres_s"] = results["fp64"]["s"]
+        out["speedup_vs_fp64"] = results["fp64"]["s"] / t_ir
+        if "bf16" in results:
+            out["bf16_basis"]["speedup_vs_fp64"] = results["fp64"]["s"] / results["bf16"]["s"]
+    if "dcgs2" in results:
+        out["one_reduction_cgs2"] = results["dcgs2"]
+        if "fp64" in results:
+            out["one_reduction_cgs2"]["speedup_vs_fp64"] = results["fp64"]["s"] / results["dcgs2"]["s"]
+        if "fp32" in results:
+            out["one_reduction_cgs2"]["speedup_vs_two_pass_cgs2"] = results["fp32"]["s"] / results["dcgs2"]["s"]
+    if "bf16" in results and "fp32" in results:
+        out["bf16_basis"]["s_per_iter_vs_fp32"] = ((results["bf16"]["s"] / results["bf16"]["iters"]) /
+                                                   (results["fp32"]["s"] / results["fp32"]["iters"]))
 
-    if not args.no_learned and os.path.exists(os.path.join(ROOT, "paper_2109_01232_amd", "chooser_weights.json")):
-        # the learned-parameter variant: features -> network -> (m, inner cap,
-        # polynomial degree), then the solve; the timed step includes the
-        # features, the network and the polynomial set-up
-        from paper_2109_01232_amd import chooser as CH
-
-        net = CH.Chooser.load()
-
-        def learned_step():
-            feats = B.gmresir_features(M, b, ws=ws)
-            m_c, capm, deg = net.choose(feats)
-            roots = B.gmresir_poly_setup(M, deg, seed=12345, ws=ws) if deg > 0 else None
-            pc = B.make_params(restart=m_c, inner="fp32", rtol=1e-10, inner_cap=m_c * capm, poly_degree=deg,
-                               check_mode=1)
-            x.zero_()
-            st, d, _ = B.gmresir_solve(M, b, x, pc, poly_roots=roots, ws=ws)
-            return (m_c, capm, deg), st, d
-
-        learned_step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            cfg_l, st_l, d_l = learned_step()
-        torch.cuda.synchronize()
-        t_l = (time.perf_counter() - t0) / args.steps
-        xs_l = x.cpu().numpy()
-        true_l = float(np.linalg.norm(system.b - A.scipy() @ xs_l) / np.linalg.norm(system.b))
-        log(f"learned {cfg_l}: {t_l:.4f} s/solve iters={d_l['iters']} resid={true_l:.3e}")
-        out["learned"] = {"s": t_l, "config": {"restart": cfg_l[0], "inner_cap": cfg_l[0] * cfg_l[1],
-                                               "poly_degree": cfg_l[2]},
-                          "iters": d_l["iters"], "status": B.status_string(st_l), "rel_resid_true": true_l,
-                          "speedup_vs_default_ir": t_ir / t_l,
-                          "includes": "features + network + polynomial set-up + solve"}
-
-    if not args.no_fp64:
-        run(p_64)
-        torch.cuda.synchronize()
-        steps64 = max(1, min(args.steps, 3))
-        t0 = time.perf_counter()
-        for _ in range(steps64):
-            d_64 = run(p_64)
-        torch.cuda.synchronize()
-        t_64 = (time.perf_counter() - t0) / steps64
-        log(f"FP64: {t_64:.4f} s/solve iters={d_64['iters']}")
-        out["fp64_gmres_s"] = t_64
-        out["fp64_iters"] = d_64["iters"]
-        out["fp64_rel_resid_true"] = d_64["rel_resid_true"]
-        out["speedup_vs_fp64"] = t_64 / t_ir
-        if "learned" in out:
-            out["learned"]["speedup_vs_fp64"] = t_64 / out["learned"]["s"]
-
-    if not args.no_fd:
-        # GMRES-FD: fp32 GMRES(m) up to the switch point, then fp64 GMRES(m)
-        # from its solution; the paper sweeps the switch point
-        fd = []
-        for sw in [int(v) for v in args.fd_switch.split(",") if v]:
-            p_fd = B.make_params(restart=args.restart, inner="fp32", basis=args.basis, rtol=1e-10, check_mode=1)
-            x.zero_()
-            B.gmresir_solve_fd(M, b, x, p_fd, sw, ws=ws)
-            torch.cuda.synchronize()
-            reps = max(1, min(args.steps, 2))
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                x.zero_()
-                st_f, d_f, _ = B.gmresir_solve_fd(M, b, x, p_fd, sw, ws=ws)
-            torch.cuda.synchronize()
-            t_f = (time.perf_counter() - t0) / reps
-            xs_f = x.cpu().numpy()
-            true_f = float(np.linalg.norm(system.b - A.scipy() @ xs_f) / np.linalg.norm(system.b))
-            log(f"FD switch {sw}: {t_f:.4f} s/solve iters={d_f['iters']} resid={true_f:.3e}")
-            fd.append({"switch": sw, "s": t_f, "iters": d_f["iters"], "status": B.status_string(st_f),
-                       "rel_resid_true": true_f})
-        out["gmres_fd"] = {"switch_points": fd,
-                           "what": "fp32 GMRES(m) for `switch` iterations, then fp64 GMRES(m) from its solution"}
-
-    if not args.no_bj:
-        # GMRES-IR with a right block-Jacobi preconditioner (fp32 inverses of
-        # the diagonal blocks, built at the start of every solve: included)
-        bj = []
-        for bs in (8, 16, 32, 42, 64):
-            p_bj = B.make_params(restart=args.restart, inner="fp32", basis=args.basis, rtol=1e-10, check_mode=1,
-                                 bj_block=bs)
-            x.zero_()
-            B.gmresir_solve(M, b, x, p_bj, ws=ws)
-            torch.cuda.synchronize()
-            reps = max(1, min(args.steps, 2))
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                x.zero_()
-                st_b, d_b, _ = B.gmresir_solve(M, b, x, p_bj, ws=ws)
-            torch.cuda.synchronize()
-            t_b = (time.perf_counter() - t0) / reps
-            xs_b = x.cpu().numpy()
-            true_b = float(np.linalg.norm(system.b - A.scipy() @ xs_b) / np.linalg.norm(system.b))
-            log(f"block Jacobi {bs}: {t_b:.4f} s/solve iters={d_b['iters']} resid={true_b:.3e}")
-            bj.append({"block": bs, "s": t_b, "iters": d_b["iters"], "status": B.status_string(st_b),
-                       "rel_resid_true": true_b, "speedup_vs_default_ir": t_ir / t_b})
-        out["block_jacobi"] = bj
+    if not args.only and not args.no_learned and os.path.exists(
+            os.path.join(ROOT, "paper_2109_01232_amd", "chooser_weights.json")):
+        out["learned"] = learned_variant(M, b, x, ws, system, Asp, args.steps)
+        if "fp64" in results:
+            out["learned"]["speedup_vs_fp64"] = results["fp64"]["s"] / out["learned"]["s"]
 
     if not args.no_profile:
         # one more solve with HIP events around every kernel (on the solve's stream)
-        p_prof = B.make_params(restart=args.restart, inner="fp32", basis=args.basis, rtol=1e-10, check_mode=1,
-                               profile=1)
-        d_prof = run(p_prof)
+        pv = "fp32" if not args.only else args.only
+        p_prof = B.make_params(restart=m, inner="fp32" if pv != "fp64" else "fp64",
+                               basis="fp32" if pv == "dcgs2" else pv, rtol=1e-10, check_mode=1, profile=1,
+                               max_iters=args.max_iters, ortho="dcgs2" if pv == "dcgs2" else "cgs2")
+        x.zero_()
+        _, d_prof, _ = B.gmresir_solve(M, b, x, p_prof, ws=ws)
         cats = ("spmv_proj", "update_proj", "update_norm")
         dom = max(cats, key=lambda c: d_prof["cat_time_s"][c])
         tt, bb, nl = d_prof["cat_time_s"][dom], d_prof["cat_bytes"][dom], d_prof["cat_launches"][dom]
         achieved = bb / tt / 1e9 if tt > 0 else 0.0
-        # a plain device copy on the same GPU, for context beside the published peak
-        src_c = torch.empty(64 << 20, dtype=torch.float32, device="cuda").uniform_()
-        dst_c = torch.empty_like(src_c)
-        dst_c.copy_(src_c)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            dst_c.copy_(src_c)
-        e1.record()
-        torch.cuda.synchronize()
-        copy_gbps = 10 * 2 * src_c.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        del src_c, dst_c
-        default_workload = args.n == 1000 and args.seed == 0 and args.restart == 50 and args.basis == "fp32"
-        traffic = measured_traffic(dom) if default_workload else None
+        copy_gbps = device_copy_rate()
+        traffic = measured_traffic(dom) if (args.seed == 0 and m == 50 and pv == "fp32") else None
         out["roofline"] = {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom, "variant": pv,
             "avg_launch_us": tt / max(nl, 1) * 1e6, "avg_bytes_per_launch": bb / max(nl, 1),
-            "measured_copy_GBps": copy_gbps,
+            "launches": nl, "measured_copy_GBps": copy_gbps,
+            "bytes_model": "SpMV (4 + 4) nnz + 4 (N + 1) + 2*4 N (x read, w written; 4-byte column indices) + "
+                           "4 N per basis column read or written (first CGS2 projection fused)",
         }
-        out["breakdown_ir"] = {
+        out["breakdown"] = {
             c: {"s": d_prof["cat_time_s"][c], "GBps": (d_prof["cat_bytes"][c] / d_prof["cat_time_s"][c] / 1e9
                                                       if d_prof["cat_time_s"][c] > 0 else 0.0),
                 "launches": d_prof["cat_launches"][c]}
             for c in B.CATEGORIES if d_prof["cat_launches"][c] > 0
         }
-        if not args.no_fp64:
-            d64p = run(B.make_params(restart=args.restart, inner="fp64", rtol=1e-10, check_mode=1, profile=1))
-            out["breakdown_fp64"] = {
-                c: {"s": d64p["cat_time_s"][c], "GBps": (d64p["cat_bytes"][c] / d64p["cat_time_s"][c] / 1e9
-                                                        if d64p["cat_time_s"][c] > 0 else 0.0),
-                    "launches": d64p["cat_launches"][c]}
-                for c in B.CATEGORIES if d64p["cat_launches"][c] > 0
-            }
 
-    if "fp64_gmres_s" in out:
-        for f in out.get("gmres_fd", {}).get("switch_points", []) + out.get("block_jacobi", []):
-            f["speedup_vs_fp64"] = out["fp64_gmres_s"] / f["s"]
+    if not args.only and not args.no_extras:
+        out["extras"] = extras(args, ws, learned=not args.no_learned)
 
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle sample)")
-        out["cpu_baseline"] = cpu_baseline(system, d_ir["iters"])
+    if not args.no_cpu_baseline and not args.only:
+        log("cpu oracle: whole fp32 GMRES-IR and fp64 GMRES solves of the same system")
+        ir, t_orc, d64, t_orc64 = cpu_oracle(system)
+        x_or = ir.x
+        for name, xs in sols.items():
+            key = {"fp32": None, "bf16": "bf16_basis", "fp64": "fp64_gmres", "dcgs2": "one_reduction_cgs2"}[name]
+            e = rel_err(xs, x_or)
+            if key is None:
+                out["sol_err_vs_oracle"] = e
+            else:
+                out[key]["sol_err_vs_oracle"] = e
+        if "learned" in out and "x" in out["learned"]:
+            out["learned"]["sol_err_vs_oracle"] = rel_err(out["learned"].pop("x"), x_or)
+        out["oracle_solution"] = {"method": "oracle fp32 GMRES-IR(50), rtol 1e-10", "iters": ir.iters,
+                                  "rel_resid": ir.rel_resid, "sol_err_vs_u": rel_err(x_or, system.u),
+                                  "fp64_gmres_x_vs_ir_x": rel_err(d64.x, x_or)}
+        out["cpu_baseline"] = {
+            "value": t_orc,
+            "unit": "s",
+            "cores": int(blas_threads()),
+            "kind": "oracle",
+            "sample": (f"the whole solve, not a sample: the oracle's fp32 GMRES-IR(50) on the same 27-point 128^3 "
+                       f"system to 1e-10 ({ir.iters} inner iterations, {ir.refinements} refinements); its "
+                       f"fp64 GMRES(50) solve took {t_orc64:.1f} s ({d64.iters} iterations)"),
+            "fp64_gmres_s": t_orc64,
+            "threads_note": "the dense products (V^T w, V h) run on the BLAS thread pool (cores); the scipy SpMV "
+                            "and the Givens loop run on one thread",
+            "cpu": platform.processor() or platform.machine(),
+            "nproc": os.cpu_count(),
+        }
+    out.get("learned", {}).pop("x", None)
 
     print(json.dumps(out), flush=True)
     if args.suite:
         suite(args)
+
+
+def device_copy_rate():
+    """A plain 256 MiB device copy on the same GPU, for context beside the published peak."""
+    import torch
+
+    src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    return 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def learned_variant(M, b, x, ws, system, Asp, steps):
+    """features -> network -> (m, inner cap, polynomial degree), then the
+    solve; the timed step includes the features, the network and the
+    polynomial set-up."""
+    import numpy as np
+    import torch
+
+    from paper_2109_01232_amd import binding as B
+    from paper_2109_01232_amd import chooser as CH
+
+    net = CH.Chooser.load()
+
+    def step():
+        feats = B.gmresir_features(M, b, ws=ws)
+        m_c, capm, deg = net.choose(feats)
+        roots = B.gmresir_poly_setup(M, deg, seed=12345, ws=ws) if deg > 0 else None
+        pc = B.make_params(restart=m_c, inner="fp32", rtol=1e-10, inner_cap=m_c * capm, poly_degree=deg,
+                           check_mode=1)
+        x.zero_()
+        st, d, _ = B.gmresir_solve(M, b, x, pc, poly_roots=roots, ws=ws)
+        return (m_c, capm, deg), st, d
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cfg, st, d = step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / max(steps, 1)
+    xs = x.cpu().numpy()
+    true = float(np.linalg.norm(system.b - Asp @ xs) / np.linalg.norm(system.b))
+    log(f"learned {cfg}: {t:.4f} s/solve iters={d['iters']} resid={true:.3e}")
+    return {"s": t, "config": {"restart": cfg[0], "inner_cap": cfg[0] * cfg[1], "poly_degree": cfg[2]},
+            "iters": d["iters"], "status": B.status_string(st), "rel_resid_true": true,
+            "converged": bool(true <= 1e-10), "sol_err_vs_u": rel_err(xs, system.u),
+            "includes": "features + network + polynomial set-up + solve", "x": xs}
+
+
+def extras(args, ws, learned=True):
+    """One timed solve each (after a warm-up) on the 2D 1000^2 and 3D 150^3
+    systems: GMRES-IR fp32 and fp64 GMRES (150^3 also with a degree-10
+    polynomial, set-up excluded; 1000^2 also the learned-parameter variant,
+    whose training population is 2D/3D convection-diffusion).  The oracle's
+    whole solves of these systems take minutes, so their errors against it
+    are not in the default line."""
+    import numpy as np
+    import torch
+
+    from paper_2109_01232_amd import binding as B
+    from paper_2109_01232_amd import problems as P
+
+    res = {}
+    for key, make, m, cases in (
+            ("convdiff2d_1000^2_5pt_seed0", lambda: P.convdiff2d_system(0), 50,
+             [("fp32", "fp32", 0), ("fp64", "fp64", 0)]),
+            ("aniso3d_150^3_7pt_seed0", lambda: P.aniso3d_system(0), 100,
+             [("fp32", "fp32", 0), ("fp32", "fp32", 10), ("fp64", "fp64", 0)])):
+        log("extra", key)
+        s = make()
+        Mx = B.Matrix.from_csr(s.A)
+        bx = torch.from_numpy(s.b).cuda()
+        xx = torch.zeros_like(bx)
+        Asp = s.A.scipy()
+        rows = {}
+        for inner, basis, deg in cases:
+            roots = B.gmresir_poly_setup(Mx, deg, seed=12345, ws=ws) if deg else None
+            p = B.make_params(restart=m, inner=inner, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg)
+            xx.zero_()
+            B.gmresir_solve(Mx, bx, xx, p, poly_roots=roots, ws=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xx.zero_()
+            st, d, _ = B.gmresir_solve(Mx, bx, xx, p, poly_roots=roots, ws=ws)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            xs = xx.cpu().numpy()
+            true = float(np.linalg.norm(s.b - Asp @ xs) / np.linalg.norm(s.b))
+            label = f"{inner}" + (f"_poly{deg}" if deg else "")
+            rows[label] = {"s": t, "iters": d["iters"], "status": B.status_string(st), "rel_resid_true": true,
+                           "converged": bool(true <= 1e-10), "sol_err_vs_u": rel_err(xs, s.u)}
+            log(f"  {label}: {t:.4f} s iters={d['iters']} resid={true:.2e}")
+        if learned and key.startswith("convdiff2d") and os.path.exists(
+                os.path.join(ROOT, "paper_2109_01232_amd", "chooser_weights.json")):
+            lv = learned_variant(Mx, bx, xx, ws, s, Asp, 1)
+            lv.pop("x", None)
+            rows["learned"] = lv
+        if "fp64" in rows:
+            for k, v in rows.items():
+                v["speedup_vs_fp64"] = rows["fp64"]["s"] / v["s"]
+        res[key] = {"N": s.A.n, "nnz": s.A.nnz, "restart": m, "solves": rows}
+        Mx.close()
+        del Mx
+    return res
 
 
 def spmv_study(calls=1000, reps=3):
@@ -441,7 +514,10 @@ def time_solves(M, b, p, roots, ws, steps):
 
 
 def suite(args):
-    """Time-to-1e-10 on the other configurations (separate JSON lines)."""
+    """Time-to-1e-10 on the other configurations and variants (one JSON line
+    per solve).  A case is (inner, basis, restart, degree, extra) with extra
+    one of {}, {"bj": block size}, {"fd": switch point} or {"poly_prec": "fp32"}
+    (an fp32 polynomial applied to fp64 vectors in fp64 GMRES)."""
     import numpy as np
     import torch
 
@@ -450,31 +526,63 @@ def suite(args):
 
     steps = max(1, min(args.steps, 3))
     ws = B.Workspace()
+
+    def laplace3d(n):
+        # stand-in for the paper's Laplace3D200 (Galeri 7-point Laplacian on a
+        # 200^3 grid): b = ones, the paper's default right-hand side
+        A = P.stencil_matrix("laplace3d_7", n)
+        return P.System(f"laplace3d_{n}", A, np.ones(A.n), None, dict(n=n, rhs="ones"))
+
+    c = lambda inner, basis, m, deg=0, **extra: (inner, basis, m, deg, extra)
     # systems are generated only for the cases that run
-    cases = [("aniso3d_150_7pt", lambda: P.aniso3d_system(0),
-              [("fp64", "fp64", 100, 0), ("fp32", "fp32", 100, 0), ("fp32", "fp32", 100, 10),
-               ("fp32", "fp32", 100, 20), ("fp32", "fp32", 100, 30), ("fp32", "fp32", 100, 40),
-               # fp64 GMRES(100) with the polynomial in fp64, and in fp32 ("fp64p32": an fp32 p(A)
-               # applied to fp64 vectors, everything else fp64)
-               ("fp64", "fp64", 100, 10), ("fp64p32", "fp64", 100, 10),
-               ("fp64", "fp64", 100, 40), ("fp64p32", "fp64", 100, 40)]),
-             ("varcoef27_128", lambda: P.varcoef27_system(0),
-              [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0), ("fp32", "bf16", 50, 0)])]
+    cases = [
+        ("aniso3d_150_7pt", lambda: P.aniso3d_system(0),
+         [c("fp64", "fp64", 100), c("fp32", "fp32", 100), c("fp32", "fp32", 100, ortho="dcgs2"),
+          c("fp32", "fp32", 100, 10), c("fp32", "fp32", 100, 10, ortho="dcgs2"), c("fp32", "fp32", 100, 20),
+          c("fp32", "fp32", 100, 30), c("fp32", "fp32", 100, 40),
+          c("fp64", "fp64", 100, 10), c("fp64", "fp64", 100, 10, poly_prec="fp32"),
+          c("fp64", "fp64", 100, 40), c("fp64", "fp64", 100, 40, poly_prec="fp32")]),
+        ("varcoef27_128", lambda: P.varcoef27_system(0),
+         [c("fp64", "fp64", 50), c("fp32", "fp32", 50), c("fp32", "bf16", 50), c("fp32", "fp32", 50, ortho="dcgs2"),
+          c("fp64", "fp64", 50, ortho="dcgs2")]),
+        # GMRES-FD switch points and block Jacobi on the 2D system (Sections "GMRES-IR vs GMRES-FD",
+        # "SpMV Speedup: A Large Test Set")
+        ("convdiff2d_1000", lambda: P.convdiff2d_system(0),
+         [c("fp64", "fp64", 50), c("fp32", "fp32", 50), c("fp32", "fp32", 50, ortho="dcgs2"),
+          c("fp64", "fp64", 50, ortho="dcgs2")]
+         + [c("fp32", "fp32", 50, fd=sw) for sw in (500, 1000, 2000)]
+         + [c("fp32", "fp32", 50, bj=bs) for bs in (8, 16, 32, 42, 64)]),
+        # the paper's two 3D Laplacian studies: the IR-vs-FD switch point (Section "GMRES-IR vs
+        # GMRES-FD") and the fp32 polynomial's loss of accuracy over degrees 10..70 in fp64 GMRES
+        # (Section "Convergence and Kernel Speedup for Preconditioned GMRES vs GMRES-IR")
+        ("laplace3d_200", lambda: laplace3d(200),
+         [c("fp64", "fp64", 50), c("fp32", "fp32", 50)]
+         + [c("fp32", "fp32", 50, fd=sw) for sw in (250, 500, 1000, 2000, 3000)]
+         + [c("fp64", "fp64", 50, d, **pp) for d in (10, 20, 30, 40, 50, 60, 70)
+            for pp in ({}, {"poly_prec": "fp32"})]),
+    ]
     for seed in range(1, 5):
-        # the headline workload at its other seeds (Peclet number drawn per seed)
+        # the 2D system at its other seeds (Peclet number drawn per seed)
         cases.append((f"convdiff2d_1000_seed{seed}", lambda seed=seed: P.convdiff2d_system(seed),
-                      [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0)]))
+                      [c("fp64", "fp64", 50), c("fp32", "fp32", 50)]))
     cases.append(("convdiff2d_64_parity", P.parity_system,
-                  [("fp64", "fp64", 50, 0), ("fp32", "fp32", 50, 0), ("fp32", "bf16", 50, 0)]))
+                  [c("fp64", "fp64", 50), c("fp32", "fp32", 50), c("fp32", "bf16", 50)]))
+
+    def label_of(name, inner, basis, m, deg, extra):
+        tail = "".join(f"/{k}{v}" for k, v in sorted(extra.items()))
+        return f"{name}/{inner}/{basis}/{m}/{deg}{tail}"
+
     for name, make_system, cfgs in cases:
-        if args.suite_case and not any(args.suite_case in f"{name}/{i}/{b}/{m}/{d}" for i, b, m, d in cfgs):
+        labels = [label_of(name, *cf) for cf in cfgs]
+        if args.suite_case and not any(args.suite_case in lb for lb in labels):
             continue
         log("suite", name)
         sysm = make_system()
         M = B.Matrix.from_csr(sysm.A)
-        b = torch.from_numpy(sysm.b).cuda()
-        for inner, basis, m, deg in cfgs:
-            label = f"{name}/{inner}/{basis}/{m}/{deg}"
+        b = torch.from_numpy(np.asarray(sysm.b, dtype=np.float64)).cuda()
+        Asp = sysm.A.scipy()
+        bnorm = float(np.linalg.norm(sysm.b))
+        for (inner, basis, m, deg, extra), label in zip(cfgs, labels):
             if args.suite_case and args.suite_case not in label:
                 continue
             roots, t_setup = None, 0.0
@@ -484,27 +592,41 @@ def suite(args):
                 roots = B.gmresir_poly_setup(M, deg, seed=12345, ws=ws)
                 torch.cuda.synchronize()
                 t_setup = time.perf_counter() - t0
-            pprec = "fp32" if inner == "fp64p32" else None
-            inner_p = "fp64" if inner == "fp64p32" else inner
-            p = B.make_params(restart=m, inner=inner_p, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg,
-                              poly_prec=pprec)
-            t, st, d, x = time_solves(M, b, p, roots, ws, steps)
+            kw = dict(restart=m, inner=inner, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg,
+                      poly_prec=extra.get("poly_prec"), bj_block=extra.get("bj", 0), ortho=extra.get("ortho", 0))
+            p = B.make_params(**kw)
+            if "fd" in extra:
+                x = torch.zeros_like(b)
+                B.gmresir_solve_fd(M, b, x, p, extra["fd"], ws=ws)  # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    x.zero_()
+                    st, d, _ = B.gmresir_solve_fd(M, b, x, p, extra["fd"], ws=ws)
+                torch.cuda.synchronize()
+                t = (time.perf_counter() - t0) / steps
+                gbps = {}
+            else:
+                t, st, d, x = time_solves(M, b, p, roots, ws, steps)
+                x.zero_()
+                _, dp, _ = B.gmresir_solve(M, b, x, B.make_params(profile=1, **kw), poly_roots=roots, ws=ws)
+                gbps = {k: (dp["cat_bytes"][k] / dp["cat_time_s"][k] / 1e9) for k in B.CATEGORIES
+                        if dp["cat_time_s"][k] > 0}
+                x.zero_()
+                B.gmresir_solve(M, b, x, p, poly_roots=roots, ws=ws)
             xs = x.cpu().numpy()
-            true = float(np.linalg.norm(sysm.b - sysm.A.scipy() @ xs) / np.linalg.norm(sysm.b))
-            prof = B.make_params(restart=m, inner=inner_p, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg,
-                                 profile=1, poly_prec=pprec)
-            x.zero_()
-            _, dp, _ = B.gmresir_solve(M, b, x, prof, poly_roots=roots, ws=ws)
-            gbps = {c: (dp["cat_bytes"][c] / dp["cat_time_s"][c] / 1e9) for c in B.CATEGORIES
-                    if dp["cat_time_s"][c] > 0}
-            rec = {"suite": name, "case": label, "N": sysm.A.n, "nnz": sysm.A.nnz, "meta": {k: v for k, v in sysm.meta.items()
-                                                                              if isinstance(v, (int, float, str))},
-                   "inner": inner, "basis": basis, "restart": m,
-                   "poly_degree": deg, "status": st, "time_to_1e-10_s": t, "poly_setup_s": t_setup,
+            true = float(np.linalg.norm(sysm.b - Asp @ xs) / bnorm)
+            rec = {"suite": name, "case": label, "N": sysm.A.n, "nnz": sysm.A.nnz,
+                   "meta": {k: v for k, v in sysm.meta.items() if isinstance(v, (int, float, str))},
+                   "inner": inner, "basis": basis, "restart": m, "poly_degree": deg, **extra,
+                   "status": B.status_string(st), "time_to_1e-10_s": t, "poly_setup_s": t_setup,
                    "iters": d["iters"], "refinements": d["refinements"], "rel_resid_true": true,
-                   "sol_err_vs_u": float(np.linalg.norm(xs - sysm.u) / np.linalg.norm(sysm.u)),
+                   "converged": bool(true <= 1e-10),
+                   "sol_err_vs_u": (rel_err(xs, sysm.u) if sysm.u is not None else None),
                    "GBps_by_category": gbps}
+            log(f"  {label}: {t:.4f} s iters={d['iters']} restarts={d['refinements']} resid={true:.2e}")
             print(json.dumps(rec), flush=True)
+        M.close()
         del M
 
 

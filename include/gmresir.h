@@ -60,9 +60,11 @@ enum gmresir_precision { GMRESIR_FP64 = 0, GMRESIR_FP32 = 1, GMRESIR_BF16 = 2 };
    (SpMV, GEMV-Trans, GEMV-NoTrans, Norm, Other), merged where this library
    fuses the operations into one kernel. */
 enum gmresir_category {
-  GMRESIR_CAT_SPMV_PROJ = 0,   /* w = A v_j and h1 = V^T w (first CGS pass projection) */
+  GMRESIR_CAT_SPMV_PROJ = 0,   /* w = A v_j and h1 = V^T w (first CGS pass projection); ortho 1: the
+                                  SpMV with the partial sums of the iteration's one reduction */
   GMRESIR_CAT_UPDATE_PROJ = 1, /* w -= V h1 and h2 = V^T w (second pass projection) */
-  GMRESIR_CAT_UPDATE_NORM = 2, /* w -= V h2 and the partial sums of ||w||^2 */
+  GMRESIR_CAT_UPDATE_NORM = 2, /* w -= V h2 and the partial sums of ||w||^2; ortho 1: the update sweep
+                                  (second pass and normalisation of v_j, first pass of the next vector) */
   GMRESIR_CAT_POLY = 3,        /* SpMV steps of p(A) */
   GMRESIR_CAT_REFINE = 4,      /* correction x += gamma V y, r = b - A x (fp64), cast of r */
   GMRESIR_CAT_OTHER = 5,       /* fallbacks for restart lengths beyond the fused limit */
@@ -99,7 +101,13 @@ typedef struct {
                           copy of A; the fp64 solve keeps M in fp64): each block is inverted by
                           Gauss-Jordan elimination with partial pivoting at the start of every
                           solve.  Excludes poly_degree > 0.  A singular block gives NUMERIC. */
-  int32_t reserved;    /* must be 0 */
+  int32_t ortho;       /* 0: CGS2 as two separate passes per iteration (Section "GMRES"): three sweeps
+                          of the basis and three reductions; 1: the same two classical Gram-Schmidt
+                          passes with the second pass and the normalisation delayed by one
+                          iteration (delayed reorthogonalisation, Bielich et al., Parallel Computing
+                          2022): one reduction and two sweeps of the basis per iteration, results
+                          equal to CGS2's in exact arithmetic.  1 needs basis_prec = inner_prec
+                          (no BF16) and restart <= 128. */
 } gmresir_params;
 
 typedef struct {

@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("poly_prec", ctypes.c_int32),
         ("bj_block", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("ortho", ctypes.c_int32),
     ]
 
 
@@ -256,7 +256,7 @@ class Matrix:
 
 
 def make_params(restart=50, inner="fp32", basis=None, rtol=1e-10, max_iters=1_000_000, inner_cap=0,
-                poly_degree=0, check_mode=1, profile=0, poly_prec=None, bj_block=0) -> Params:
+                poly_degree=0, check_mode=1, profile=0, poly_prec=None, bj_block=0, ortho=0) -> Params:
     if basis is None:
         basis = "fp64" if inner == "fp64" else "fp32"
     p = Params()
@@ -271,7 +271,7 @@ def make_params(restart=50, inner="fp32", basis=None, rtol=1e-10, max_iters=1_00
     p.profile = profile
     p.poly_prec = 0 if poly_prec is None else PREC[poly_prec]
     p.bj_block = bj_block
-    p.reserved = 0
+    p.ortho = {"cgs2": 0, "dcgs2": 1}.get(ortho, ortho)
     return p
 
 

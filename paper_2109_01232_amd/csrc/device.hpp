@@ -88,6 +88,7 @@ struct StateHdr {
   double stop_abs;  // implicit early exit when |g_{j+1}| <= stop_abs (< 0: off)
   double rtol;
   double implicit;  // |g_{k}| of the last step (implicit residual, cycle units)
+  double lsrho;     // one-reduction CGS2: norm of the vector the next update normalises
   int32_t check_mode;
   int32_t k;            // Arnoldi steps completed in the current cycle
   int32_t flags;        // F_* of the current cycle
@@ -115,6 +116,8 @@ struct State {
   double* g;     // m+1   rotated right-hand side
   double* y;     // m     least-squares solution of the finished cycle
   double* hist;  // m     |g_{j+1}| / gamma_in per step
+  double* red;   // one-reduction CGS2: column sums of the iteration's reduction (alpha, gam, a, c)
+  double* dco;   // one-reduction CGS2: update coefficients d of the iteration
   int ld;        // m+1
   __host__ __device__ double* h1_of(int j) const { return (j & 1) ? h1x : h1; }
 };

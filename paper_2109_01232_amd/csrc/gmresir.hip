@@ -22,6 +22,7 @@
 
 #include "gmresir.h"
 #include "kernels.hpp"
+#include "lowsync.hpp"
 
 using namespace gir;
 
@@ -158,6 +159,7 @@ struct Layout {
   int sT, sS;
   int bj;  // block-Jacobi block size (0: none)
   bool multi, poly;
+  bool ls;  // one-reduction CGS2 (ortho = 1)
 };
 
 bool valid_params(const gmresir_params* p, const char** why) {
@@ -177,7 +179,10 @@ bool valid_params(const gmresir_params* p, const char** why) {
   if (p->poly_prec != 0 && p->poly_prec != GMRESIR_FP32) return *why = "poly_prec must be 0 or FP32", false;
   if (p->bj_block < 0 || p->bj_block > BJ_MAX) return *why = "bj_block must be in [0, 64]", false;
   if (p->bj_block > 0 && p->poly_degree > 0) return *why = "bj_block and poly_degree exclude each other", false;
-  if (p->reserved != 0) return *why = "reserved must be 0", false;
+  if (p->ortho != 0 && p->ortho != 1) return *why = "ortho must be 0 or 1", false;
+  if (p->ortho == 1 && p->basis_prec == GMRESIR_BF16)
+    return *why = "the one-reduction CGS2 (ortho 1) keeps the basis in the inner precision (no BF16)", false;
+  if (p->ortho == 1 && p->restart > LS_MAX_RESTART) return *why = "ortho 1 needs restart <= 128", false;
   return true;
 }
 
@@ -190,6 +195,7 @@ Layout make_layout(int64_t n, const gmresir_params* p) {
   L.multi = cap > p->restart;
   L.poly = p->poly_degree > 0;
   L.bj = p->bj_block;
+  L.ls = p->ortho == 1;
   L.ldv = (long)((n + 127) / 128 * 128);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -213,10 +219,10 @@ Layout make_layout(int64_t n, const gmresir_params* p) {
   L.p0 = L.poly ? take(vecT) : 0;
   L.p1 = L.poly ? take(vecT) : 0;
   L.p2 = L.poly ? take(vecT) : 0;
-  L.part = take((size_t)MAX_BLOCKS * PART_COLS * 8);
+  L.part = take((size_t)MAX_BLOCKS * (L.ls ? std::max(PART_COLS, LS_PART_COLS) : PART_COLS) * 8);
   L.hdr = take(sizeof(StateHdr));
   size_t m = L.m;
-  size_t arr = (3 * (m + 2) + 2 * (m + 1) * m + 2 * m + (m + 2) + 2 * m) * sizeof(double);
+  size_t arr = (3 * (m + 2) + 2 * (m + 1) * m + 2 * m + (m + 2) + 2 * m + LS_PART_COLS + (m + 2)) * sizeof(double);
   L.arr = take(arr);
   L.total = o;
   return L;
@@ -247,6 +253,10 @@ State state_of(char* ws, const Layout& L) {
   st.y = a;
   a += m;
   st.hist = a;
+  a += m;
+  st.red = a;
+  a += LS_PART_COLS;
+  st.dco = a;
   return st;
 }
 
@@ -508,11 +518,12 @@ struct Ctx {
   size_t lds_64() const { return A->sell ? 0 : (size_t)A->lds_nnz * sizeof(double); }
   double sT() const { return (double)sizeof(T); }
   double sS() const { return (double)sizeof(S); }
-  // values + column indices (4 bytes, or 2 for the 16-bit offsets of the
-  // sliced copy) + row pointers; sell_path: the launch reads the sliced copy
+  // algorithmic bytes of the CSR arrays: values + 4-byte column indices +
+  // row pointers (what the CSR SpMV must read once; the sliced copy's 16-bit
+  // column offsets read less, which the counter traffic shows)
   double spmv_bytes(bool sell_path = true) const {
-    const double idx = (sell_path && A->sell && A->sell_d16) ? 2.0 : 4.0;
-    return (sT() + idx) * A->nnz + 4.0 * (A->n + 1);
+    (void)sell_path;
+    return (sT() + 4.0) * A->nnz + 4.0 * (A->n + 1);
   }
 
   T* buf(int b, T* src) {
@@ -575,7 +586,7 @@ struct Ctx {
       }
     };
     const size_t lds = A->sell ? 0 : (size_t)A->lds_nnz * sizeof(float);
-    const double idx = (A->sell && A->sell_d16) ? 2.0 : 4.0;
+    const double idx = 4.0;  // algorithmic: 4-byte column indices
     for (size_t s = 0; s < prog.size(); ++s) {
       const PStep& ps = prog[s];
       PolyCoef<float> cf;
@@ -790,6 +801,141 @@ struct Ctx {
     update_norm(j);
   }
 
+  // -------------------------------------------------------------------------
+  // one-reduction CGS2 (ortho = 1): per iteration the SpMV with the partial
+  // sums of the one reduction, the column sums, the dense step and the update
+  // sweep; p = A M^{-1} q lives in w1, the once-orthogonalised q in w2
+  // -------------------------------------------------------------------------
+
+  T* q_ls() const { return w2; }
+  T* p_ls() const { return w1; }
+  static int ls_ncols(int j, bool has_p) { return LS_A + (has_p ? 2 * j : j); }
+
+  void ls_reduce(int ncols, int producer_grid) {
+    auto kern = k_reduce_cols<T>;
+    prof->launch(GMRESIR_CAT_TAIL, 0.0, kern, dim3((ncols + NWAVES - 1) / NWAVES), dim3(BLOCK), 0, stream,
+                 (const T*)part, ncols, producer_grid, st.red);
+  }
+
+  template <int SLOTS, int NW, bool SCALED>
+  void ls_spmv_dots_sell_launch(const T* gsrc, const T* own, int j, bool own_read) {
+    auto kern = k_ls_spmv_dots_sell<T, S, SLOTS, SCALED, NW>;
+    constexpr int SPS = (sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS) / SELL_C;  // slices per stage
+    const int g = std::max(1, std::min(resident_grid((const void*)kern, 0, NW * WAVE), (A->nslices + SPS - 1) / SPS));
+    const double b = spmv_bytes() + 2.0 * sT() * n + sS() * n * j + (SCALED ? sS() * n : own_read ? sT() * n : 0.0);
+    prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(NW * WAVE), 0, stream, Ain, gsrc, own, V, L.ldv, j,
+                 p_ls(), st, part);
+    ls_reduce(ls_ncols(j, true), g);
+  }
+
+  template <bool SCALED>
+  void ls_spmv_dots_sell(const T* gsrc, const T* own, int j, bool own_read) {
+    if (j <= 16) ls_spmv_dots_sell_launch<2, 8, SCALED>(gsrc, own, j, own_read);
+    else if (j <= 32) ls_spmv_dots_sell_launch<4, 8, SCALED>(gsrc, own, j, own_read);
+    else if (j <= 64) ls_spmv_dots_sell_launch<8, 8, SCALED>(gsrc, own, j, own_read);
+    else ls_spmv_dots_sell_launch<16, 8, SCALED>(gsrc, own, j, own_read);
+  }
+
+  template <int SLOTS, bool HAS_P>
+  void ls_dots_launch(const T* q, int j) {
+    constexpr int WV = NWAVES;
+    auto kern = k_ls_dots<T, S, SLOTS, HAS_P, WV>;
+    const int g = grid_rows((const void*)kern, n, WV * WAVE);
+    const double b = sS() * n * j + sT() * n * (HAS_P ? 2 : 1);
+    prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(WV * WAVE), 0, stream, n, q, (const T*)p_ls(),
+                 (const S*)V, L.ldv, j, st, part);
+    ls_reduce(ls_ncols(j, HAS_P), g);
+  }
+
+  template <bool HAS_P>
+  void ls_dots(const T* q, int j) {
+    if (j <= 16) ls_dots_launch<4, HAS_P>(q, j);
+    else if (j <= 32) ls_dots_launch<8, HAS_P>(q, j);
+    else if (j <= 64) ls_dots_launch<16, HAS_P>(q, j);
+    else ls_dots_launch<32, HAS_P>(q, j);
+  }
+
+  // plain SpMV p = A src that skips a stopped cycle (matrices without a fused sliced kernel)
+  void ls_spmv(const T* src) {
+    auto kern = k_ls_spmv<T>;
+    prof->launch(GMRESIR_CAT_SPMV_PROJ, spmv_bytes() + 2.0 * sT() * n, kern, dim3(grid_spmv(A)), dim3(BLOCK), lds_in(),
+                 stream, Ain, src, p_ls(), st);
+  }
+
+  void ls_dense(int j, int kmax) {
+    prof->launch(GMRESIR_CAT_TAIL, 0.0, k_ls_dense<T>, dim3(1), dim3(BLOCK), 0, stream, st, (const double*)st.red, st.dco,
+                 j, kmax);
+  }
+
+  void ls_update(int j) {
+    auto kern = k_ls_update<T, S>;
+    const int g = grid_rows((const void*)kern, n);
+    const double b = sS() * n * (j + 1) + sT() * n * (j > 0 ? 3 : 2);
+    prof->launch(GMRESIR_CAT_UPDATE_NORM, b, kern, dim3(g), dim3(BLOCK), 0, stream, n, (const T*)p_ls(), q_ls(), V,
+                 L.ldv, j, st, (const double*)st.dco);
+  }
+
+  // iteration j: p = A M^{-1} q_j (j = 0: A M^{-1} v_0) with the one
+  // reduction, the dense step (completes column j-1), the update sweep
+  void ls_iteration(int j, int kmax) {
+    prof->tag = j;
+    prof->early = true;
+    const bool precond = L.bj > 0 || poly_on;
+    const bool fused = A->sell && A->nslices >= 1024;
+    T* q = q_ls();
+    T* v0 = (T*)V;  // S == T on this path
+    const T* gsrc = q;
+    const T* own = q;
+    if (precond) {
+      // the preconditioner's first kernel forms v_0 into V[:, 0] at j = 0
+      const T* src = j == 0 ? (const T*)wtmp : (const T*)q;
+      if (L.bj > 0) {
+        bj_apply(src, j == 0, 0, z, 1, GMRESIR_CAT_POLY, 0);
+      } else if (poly32) {
+        if (j == 0) {
+          auto kern = k_scale_narrow<T, S>;
+          const int g = grid_rows((const void*)kern, n);
+          prof->launch(GMRESIR_CAT_POLY, sT() * n + sS() * n + 4.0 * n, kern, dim3(g), dim3(BLOCK), 0, stream, n,
+                       (const T*)wtmp, V, L.ldv, 0, s32, st, (const T*)norm_part(), 0);
+        } else {
+          narrow((const double*)q, s32, 1, GMRESIR_CAT_POLY);
+        }
+        run_poly32(s32, y32, 1, GMRESIR_CAT_POLY);
+        widen(y32, (double*)z, 1, GMRESIR_CAT_POLY);
+      } else {
+        run_poly((T*)src, j == 0, 0, z, 1, GMRESIR_CAT_POLY, 0);
+      }
+      gsrc = z;
+      own = j == 0 ? v0 : q;
+    } else if (j == 0 && !fused) {
+      auto kern = k_ls_form_v0<T, S>;
+      prof->launch(GMRESIR_CAT_SPMV_PROJ, sT() * n + sS() * n, kern, dim3(grid_rows((const void*)kern, n)),
+                   dim3(BLOCK), 0, stream, n, (const T*)wtmp, V, st);
+      gsrc = own = v0;
+    }
+    if (fused) {
+      if (j == 0 && !precond) ls_spmv_dots_sell<true>(wtmp, nullptr, 0, false);
+      else ls_spmv_dots_sell<false>(gsrc, own, j, precond);
+    } else {
+      ls_spmv(gsrc);
+      ls_dots<true>(own, j);
+    }
+    ls_dense(j, kmax);
+    prof->early = false;
+    ls_update(j);
+  }
+
+  // the cycle's last column: the reduction without an SpMV, then its Givens step
+  void ls_cycle(int kmax) {
+    for (int j = 0; j < kmax; ++j) ls_iteration(j, kmax);
+    prof->tag = kmax;
+    prof->early = true;
+    ls_dots<false>(q_ls(), kmax);
+    ls_dense(kmax, kmax);
+    prof->tag = -1;
+    prof->early = false;
+  }
+
   // Small systems are bound by the host's launch rate (~5 kernels of a few
   // microseconds per step): their cycles run as one HIP graph, recorded on
   // first use and replayed for every later cycle of the same length (all
@@ -844,6 +990,12 @@ struct Ctx {
 
   // the Arnoldi steps of one cycle, ending with its last Givens step
   void cycle(int kmax) {
+    if constexpr (sizeof(S) == sizeof(T)) {
+      if (L.ls) {  // (the parameter check keeps bf16 bases off this path)
+        ls_cycle(kmax);
+        return;
+      }
+    }
     for (int j = 0; j < kmax; ++j) iteration(j, kmax);
     prof->tag = kmax - 1;
     prof->early = false;
@@ -881,7 +1033,7 @@ struct Ctx {
   void resid64(const double* x, const double* b) {
     auto kern = k_resid64;
     int g = grid_spmv_part(A, (const void*)kern, lds_64());
-    prof->launch(GMRESIR_CAT_REFINE, (A->sell && A->sell_d16 ? 10.0 : 12.0) * A->nnz + 4.0 * (A->n + 1) + 8.0 * n * 3, kern, dim3(g), dim3(BLOCK), lds_64(), stream, A64, x, b, r64, (double*)part);
+    prof->launch(GMRESIR_CAT_REFINE, 12.0 * A->nnz + 4.0 * (A->n + 1) + 8.0 * n * 3, kern, dim3(g), dim3(BLOCK), lds_64(), stream, A64, x, b, r64, (double*)part);
     sqrt_tail(g, &st.hdr->gamma);
   }
 
@@ -1233,7 +1385,7 @@ int scratch_ptr(int dev, char** out) {
 
 extern "C" {
 
-int32_t gmresir_abi_version(void) { return 3; }
+int32_t gmresir_abi_version(void) { return 4; }
 
 const char* gmresir_last_error(void) { return gir::last_error(); }
 

@@ -1017,6 +1017,7 @@ __global__ void k_init_state(State st, double rtol, int check_mode, double gamma
     hd->stop_abs = -1.0;
     hd->rtol = rtol;
     hd->implicit = 0.0;
+    hd->lsrho = 0.0;
     hd->check_mode = check_mode;
     hd->k = 0;
     hd->flags = 0;

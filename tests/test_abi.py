@@ -15,7 +15,7 @@ def test_library_exports_every_declared_function():
     assert len(names) >= 20
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.gmresir_abi_version() == 3
+    assert lib.gmresir_abi_version() == 4
 
 
 def test_status_strings_and_errors():

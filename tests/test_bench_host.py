@@ -22,6 +22,10 @@ def test_traffic_figures_follow_the_sources():
 
     h = bench.kernel_source_hash()
     assert len(h) == 64
+    if not os.path.exists(bench.TRAFFIC_FILE):
+        # no committed counter summary for the workload: no traffic figure
+        assert bench.measured_traffic("spmv_proj") is None
+        return
     with open(bench.TRAFFIC_FILE) as f:
         t = json.load(f)
     for k in ("spmv_proj", "update_proj", "update_norm"):
