@@ -220,14 +220,21 @@ class Chooser:
 def solve_with_chooser(runner: Runner, chooser: Chooser, budget_factor: float = 1.0):
     """Predicted configuration, with the fixed defaults as fallback when it
     does not reach the target.  Returns (result of the accepted run, total
-    time including any wasted attempt, configuration used)."""
+    time, configuration used, time of the choice).  The total includes the
+    features (row statistics and a 10-step fp32 Arnoldi process) and the
+    network's forward pass, which the fixed configurations do not pay, and any
+    wasted attempt."""
+    torch = runner.torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     feats = runner.features()
     cfg = chooser.choose(feats)
+    t_choice = time.perf_counter() - t0
     r = runner.run(cfg)
     if r["ok"]:
-        return r, r["time"], cfg
+        return r, t_choice + r["time"], cfg, t_choice
     d = runner.run(DEFAULT)
-    return d, r["time"] + d["time"], DEFAULT
+    return d, t_choice + r["time"] + d["time"], DEFAULT, t_choice
 
 
 def cmd_train(args):
@@ -249,9 +256,11 @@ def cmd_evaluate(args):
         R = Runner(sysm)
         R.run(DEFAULT, max_iters=200)
         base = R.run(DEFAULT)
-        r, total, cfg = solve_with_chooser(R, chooser)
+        chooser.choose(R.features())  # warm-up of the feature and network kernels
+        r, total, cfg, t_choice = solve_with_chooser(R, chooser)
         rec = {"seed": seed, "n": sysm.A.n, "default": base, "chosen": list(cfg), "chosen_run": r,
-               "chosen_total": total, "speedup": (base["time"] / total) if base["ok"] else None}
+               "choice_time": t_choice, "chosen_total": total,
+               "speedup": (base["time"] / total) if base["ok"] else None}
         for fixed in args.also:
             fc = tuple(int(v) for v in fixed.split(","))
             fr = R.run(fc)
@@ -268,7 +277,8 @@ def cmd_evaluate(args):
         summary = {"systems": len(sp), "geomean_speedup": float(np.exp(np.log(sp).mean())),
                    "median_speedup": float(np.median(sp)), "frac_improved": float(np.mean(sp > 1.0)),
                    "worst": float(sp.min()), "best": float(sp.max()),
-                   "fallbacks": int(sum(1 for r in out if not r["chosen_run"]["ok"]))}
+                   "fallbacks": int(sum(1 for r in out if not r["chosen_run"]["ok"])),
+                   "median_choice_time_s": float(np.median([r["choice_time"] for r in out]))}
         for fixed in args.also:
             fs = np.array([r["fixed_" + fixed]["speedup"] for r in out if r["fixed_" + fixed]["speedup"]])
             summary["fixed_" + fixed + "_geomean_speedup"] = float(np.exp(np.log(fs).mean()))

@@ -662,7 +662,7 @@ struct Ctx {
   // partials of ||w''||^2 written by k_update_norm (their own column, so
   // they survive the projections of the next iteration)
   T* norm_part() const { return part + (size_t)NORM_SLOT * MAX_BLOCKS; }
-  int norm_grid() const { return grid_rows((const void*)k_update_norm<T, S>, n); }
+  int norm_grid() const { return grid_rows((const void*)k_update_norm<T, S, 2 * BLOCK>, n, 2 * BLOCK); }
 
   // nB: producer blocks of the previous iteration's norm partials (0 at a
   // cycle start); the tail also makes the Givens step of iteration j - 1.
@@ -681,14 +681,28 @@ struct Ctx {
       // up to 32 columns: eight waves per block with half the column slots
       // each (same KMAX), twice the loads in flight per CU at the same number
       // of partial sums (measured on the 1000^2 system: 18.8 -> 16.4 us at
-      // k <= 16, 27.2 -> 25.0 us at k <= 32; 37.2 -> 41.1 us at k <= 64, so
-      // wider bases keep four waves)
+      // k <= 16, 27.2 -> 25.0 us at k <= 32).  Up to 64 columns eight waves
+      // pay only for rows of more than 6 nonzeros, where the SpMV part needs
+      // the loads in flight (27-point 128^3: 138 -> 122 us; 5-point 1000^2:
+      // 37.2 -> 41.1 us, so short rows keep four waves there).
       constexpr int NW = KMAX <= 32 ? 2 * NWAVES : NWAVES;
-      auto kern = k_spmv_proj_sell<T, S, KMAX / NW, SCALED, NW>;
       constexpr int SPS = (sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS) / SELL_C;  // slices per stage
-      g = std::max(1, std::min(resident_grid((const void*)kern, 0, NW * WAVE), (A->nslices + SPS - 1) / SPS));
-      prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(NW * WAVE), 0, stream, Ain, src, V, L.ldv, j, w1, st,
-                   part, (const T*)norm_part(), nB);
+      bool done = false;
+      if constexpr (KMAX == 64 || KMAX == 128) {
+        if (A->nnz > 6 * A->n) {
+          auto kern = k_spmv_proj_sell<T, S, KMAX / (2 * NWAVES), SCALED, 2 * NWAVES>;
+          g = std::max(1, std::min(resident_grid((const void*)kern, 0, 2 * NWAVES * WAVE), (A->nslices + SPS - 1) / SPS));
+          prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(2 * NWAVES * WAVE), 0, stream, Ain, src, V, L.ldv,
+                       j, w1, st, part, (const T*)norm_part(), nB);
+          done = true;
+        }
+      }
+      if (!done) {
+        auto kern = k_spmv_proj_sell<T, S, KMAX / NW, SCALED, NW>;
+        g = std::max(1, std::min(resident_grid((const void*)kern, 0, NW * WAVE), (A->nslices + SPS - 1) / SPS));
+        prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(NW * WAVE), 0, stream, Ain, src, V, L.ldv, j, w1,
+                     st, part, (const T*)norm_part(), nB);
+      }
     } else {
       auto kern = k_spmv_proj<T, S, SLOTS, SCALED>;
       g = grid_tiles_part((const void*)kern, Ain.ntiles, lds_tiled());
@@ -738,10 +752,14 @@ struct Ctx {
   void update_proj_dispatch(int k) {
     // 16-byte basis loads: 2 fp64, 4 fp32 or 8 bf16 rows per lane
     constexpr int R = 16 / sizeof(S);
+    // an fp32 basis of 33..64 columns: eight waves (the grid is capped at
+    // MAX_BLOCKS blocks; 27-point 128^3: 47.4 -> 45.3 us per launch); a bf16
+    // basis keeps four (eight measured slower: 34.5 -> 45.0 us)
+    constexpr bool W8 = sizeof(S) == 4 && sizeof(T) == 4;
     if (k <= 16) launch_update_proj<4, R, 4>(k);
     else if (k <= 32) launch_update_proj<8, R, 4>(k);
-    else if (k <= 48) launch_update_proj<12, R, 4>(k);
-    else if (k <= 64) launch_update_proj<16, R, 4>(k);
+    else if (k <= 48) launch_update_proj<W8 ? 6 : 12, R, W8 ? 8 : 4>(k);
+    else if (k <= 64) launch_update_proj<W8 ? 8 : 16, R, W8 ? 8 : 4>(k);
     // widest bases: fp32 / bf16 split the columns over eight waves (4.4 vs
     // 3.7 TB/s measured at m = 100); fp64 keeps four waves, one row per lane
     else if (k <= 128) {
@@ -761,10 +779,11 @@ struct Ctx {
     }
   }
 
+  static constexpr int NORM_NT = 2 * BLOCK;
   void update_norm(int j) {
-    auto kern = k_update_norm<T, S>;
-    int g = grid_rows((const void*)kern, n);
-    prof->launch(GMRESIR_CAT_UPDATE_NORM, sT() * n * 2 + sS() * n * (j + 1), kern, dim3(g), dim3(BLOCK), 0, stream, n, w2, wtmp, V, L.ldv, j, st, norm_part());
+    auto kern = k_update_norm<T, S, NORM_NT>;
+    prof->launch(GMRESIR_CAT_UPDATE_NORM, sT() * n * 2 + sS() * n * (j + 1), kern, dim3(norm_grid()), dim3(NORM_NT), 0,
+                 stream, n, w2, wtmp, V, L.ldv, j, st, norm_part());
   }
 
   // Givens step of the last iteration of a cycle (the others run in the
@@ -863,15 +882,17 @@ struct Ctx {
   }
 
   void ls_dense(int j, int kmax) {
-    prof->launch(GMRESIR_CAT_TAIL, 0.0, k_ls_dense<T>, dim3(1), dim3(BLOCK), 0, stream, st, (const double*)st.red, st.dco,
-                 j, kmax);
+    // dynamic LDS: the Hessenberg columns 0..j-1, rows 0..j, in inner precision
+    const size_t smem = (size_t)(j + 1) * j * sizeof(T);
+    prof->launch(GMRESIR_CAT_TAIL, 0.0, k_ls_dense<T>, dim3(1), dim3(BLOCK), smem, stream, st, (const double*)st.red,
+                 st.dco, j, kmax);
   }
 
   void ls_update(int j) {
-    auto kern = k_ls_update<T, S>;
-    const int g = grid_rows((const void*)kern, n);
+    auto kern = k_ls_update<T, S, 2 * BLOCK>;
+    const int g = grid_rows((const void*)kern, n, 2 * BLOCK);
     const double b = sS() * n * (j + 1) + sT() * n * (j > 0 ? 3 : 2);
-    prof->launch(GMRESIR_CAT_UPDATE_NORM, b, kern, dim3(g), dim3(BLOCK), 0, stream, n, (const T*)p_ls(), q_ls(), V,
+    prof->launch(GMRESIR_CAT_UPDATE_NORM, b, kern, dim3(g), dim3(2 * BLOCK), 0, stream, n, (const T*)p_ls(), q_ls(), V,
                  L.ldv, j, st, (const double*)st.dco);
   }
 

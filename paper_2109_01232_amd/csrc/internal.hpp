@@ -32,7 +32,6 @@ constexpr int SPMV_UNROLL = 5;  // nonzeros per thread whose loads are issued to
 // otherwise the row-tiled CSR kernels run.
 constexpr int SELL_C = 64;
 constexpr int SELL_MAX_ROW = 512;
-constexpr int SELL_UNROLL = 5;  // entries per lane whose loads are issued together
 inline int64_t sell_max_entries(int64_t n, int64_t nnz) { return nnz + nnz / 4 + (n < 4096 ? n : 4096) * 4; }
 
 // Upper bound of the number of tiles (every tile holds at least one row).

@@ -77,32 +77,30 @@ __device__ __forceinline__ void stage_products(const Csr& A, int p0, int len, co
 
 // One row of the sliced ELLPACK copy, summed in column order by the lane that
 // owns it (the same order, and so the same bits, as the tiled CSR kernels).
-// Loads of SELL_UNROLL entries are issued before their gathers; padding
-// entries past the row length are loaded (valid addresses) but not added.
+// Loads of U entries are issued before their gathers; padding entries past
+// the row length are loaded (valid addresses) but not added.
 // D16: the columns are 16-bit offsets from the row (rows past n: from row 0).
-template <typename T, bool D16, typename XF>
-__device__ __forceinline__ T sell_row_cols(const Csr& A, const XF& xf, int s, int r, int lane) {
+template <typename T, bool D16, int U, typename XF>
+__device__ __forceinline__ T sell_row_cols(const Csr& A, const XF& xf, int s, int r, int lane, int base, int K) {
 #pragma clang fp contract(off)
   const T* vals = (const T*)A.svals;
   const int len = r < A.n ? A.rowptr[r + 1] - A.rowptr[r] : 0;
-  const int base = A.sptr[s];
-  const int K = (A.sptr[s + 1] - base) / SELL_C;
   const int rr = r < A.n ? r : 0;
   T sum = T(0);
-  for (int k0 = 0; k0 < K; k0 += SELL_UNROLL) {
-    int cc[SELL_UNROLL];
-    T vv[SELL_UNROLL], xv[SELL_UNROLL];
+  for (int k0 = 0; k0 < K; k0 += U) {
+    int cc[U];
+    T vv[U], xv[U];
 #pragma unroll
-    for (int u = 0; u < SELL_UNROLL; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int k = k0 + u < K ? k0 + u : K - 1;
       if constexpr (D16) cc[u] = rr + (int)A.scol16[base + SELL_C * k + lane];
       else cc[u] = A.scol[base + SELL_C * k + lane];
       vv[u] = vals[base + SELL_C * k + lane];
     }
 #pragma unroll
-    for (int u = 0; u < SELL_UNROLL; ++u) xv[u] = xf(cc[u]);
+    for (int u = 0; u < U; ++u) xv[u] = xf(cc[u]);
 #pragma unroll
-    for (int u = 0; u < SELL_UNROLL; ++u) {
+    for (int u = 0; u < U; ++u) {
       const T p = vv[u] * xv[u];
       if (k0 + u < len) sum = sum + p;
     }
@@ -110,11 +108,25 @@ __device__ __forceinline__ T sell_row_cols(const Csr& A, const XF& xf, int s, in
   return sum;
 }
 
+// The entries whose loads go out together follow the slice's width K (a
+// wave-uniform value): 5 for rows of up to 5 entries, 7 up to 7, else 9 (a
+// 27-point row in three rounds; measured on the 27-point 128^3 system: SpMV +
+// projection 124 -> 119 us with 9 instead of 5, while a 5-point row loaded
+// in rounds of 9 wastes four loads per round and ran 5 % slower).
+template <typename T, bool D16, typename XF>
+__device__ __forceinline__ T sell_row_k(const Csr& A, const XF& xf, int s, int r, int lane) {
+  const int base = A.sptr[s];
+  const int K = (A.sptr[s + 1] - base) / SELL_C;
+  if (K <= 5) return sell_row_cols<T, D16, 5>(A, xf, s, r, lane, base, K);
+  if (K <= 7) return sell_row_cols<T, D16, 7>(A, xf, s, r, lane, base, K);
+  return sell_row_cols<T, D16, 9>(A, xf, s, r, lane, base, K);
+}
+
 // The column width is chosen once per slice (a wave-uniform branch), not per
 // load: a load under a branch is waited for at the branch's end.
 template <typename T, typename XF>
 __device__ __forceinline__ T sell_row(const Csr& A, const XF& xf, int s, int r, int lane) {
-  return A.d16 ? sell_row_cols<T, true>(A, xf, s, r, lane) : sell_row_cols<T, false>(A, xf, s, r, lane);
+  return A.d16 ? sell_row_k<T, true>(A, xf, s, r, lane) : sell_row_k<T, false>(A, xf, s, r, lane);
 }
 
 // SpMV over the sliced ELLPACK copy: the block takes a contiguous range of
@@ -836,23 +848,25 @@ __device__ __forceinline__ void givens_tail(const State& st, int j, int kmax, T 
 }
 
 // Each lane owns four consecutive rows (16-byte loads for fp32); the padded
-// rows past n are masked out.
-template <typename T, typename S>
-__global__ __launch_bounds__(BLOCK) void k_update_norm(int n, const T* __restrict__ w_in, T* __restrict__ wtmp,
-                                                       const S* __restrict__ V, long ldv, int j, State st,
-                                                       T* __restrict__ part) {
+// rows past n are masked out.  NT threads per block: 512 (eight waves), since
+// the grid is capped at MAX_BLOCKS blocks by the partial-sum slots and four
+// waves per block then leave half of each CU's wave slots empty.
+template <typename T, typename S, int NT>
+__global__ __launch_bounds__(NT) void k_update_norm(int n, const T* __restrict__ w_in, T* __restrict__ wtmp,
+                                                    const S* __restrict__ V, long ldv, int j, State st,
+                                                    T* __restrict__ part) {
   const int flags = load_flags(st.hdr);  // tested after h2 is staged (one round trip for both)
   __shared__ T s_h[MAX_RESTART + 2];
   __shared__ T s_vals[1];
-  __shared__ T s_scr[NWAVES * WAVE];
+  __shared__ T s_scr[16];
   const int k = j + 1;
-  for (int c = threadIdx.x; c < k; c += BLOCK) s_h[c] = (T)st.h2[c];
+  for (int c = threadIdx.x; c < k; c += NT) s_h[c] = (T)st.h2[c];
   __syncthreads();
   if (flags & F_DONE) return;
   int r0, r1;
   block_rows(n, r0, r1);
   T nrm = T(0);
-  for (int r = r0 + 4 * threadIdx.x; r < r1; r += 4 * BLOCK) {
+  for (int r = r0 + 4 * threadIdx.x; r < r1; r += 4 * NT) {
     const int nv = r1 - r < 4 ? r1 - r : 4;
     T wv[4];
     Quad<T, T>::load(w_in + r, wv);
@@ -875,10 +889,8 @@ __global__ __launch_bounds__(BLOCK) void k_update_norm(int n, const T* __restric
       }
     }
   }
-  const T bs = block_sum(nrm, s_scr);
-  if (threadIdx.x == 0) s_vals[0] = bs;
-  __syncthreads();
-  store_partials(s_vals, 1, part);
+  const T bs = block_sum_any(nrm, s_scr);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
 }
 
 // ---------------------------------------------------------------------------

@@ -303,11 +303,33 @@ __global__ __launch_bounds__(BLOCK) void k_ls_dense(State st, const double* __re
   if (s_flags & F_DONE) return;  // stop, breakdown, NaN, or the cycle's last column
   const T rho = sqrt(nrm2);
   const int ld = st.ld;
+  // H[0:j+1, 0:j] staged in LDS (dynamic, (j + 1) j entries) with coalesced
+  // loads of whole columns; a row-by-row walk through global memory made this
+  // block latency bound (j dependent-address loads per thread)
+  T* sH = dyn_lds<T>();
+  const int hj = j + 1;
+  const int tot = hj * j;
+  constexpr int BATCH = 8;  // loads in flight per thread before their LDS stores
+  for (int e0 = 0; e0 < tot; e0 += BLOCK * BATCH) {
+    T v[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int e = e0 + (int)threadIdx.x + BLOCK * u;
+      const int l = e / hj, i = e - l * hj;
+      v[u] = (e < tot && i <= l + 1) ? (T)st.Hbar[(size_t)l * ld + i] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int e = e0 + (int)threadIdx.x + BLOCK * u;
+      if (e < tot) sH[e] = v[u];
+    }
+  }
+  __syncthreads();
   // t = H[0:j+1, 0:j] a (upper Hessenberg: row i starts at column i - 1)
   T ac = T(0);
   for (int i = threadIdx.x; i <= j; i += blockDim.x) {
     T t = T(0);
-    for (int l = i > 0 ? i - 1 : 0; l < j; ++l) t += (T)st.Hbar[(size_t)l * ld + i] * s_a[l];
+    for (int l = i > 0 ? i - 1 : 0; l < j; ++l) t += sH[l * hj + i] * s_a[l];
     s_t[i] = t;
     if (i < j) {
       const T c = (T)red[LS_A + j + i];
@@ -329,14 +351,16 @@ __global__ __launch_bounds__(BLOCK) void k_ls_dense(State st, const double* __re
 // v_j = round((q - Q a) / rho) into V[:, j] and, in place,
 // q <- p / rho - V[:, 0:j+1] d (j = 0: v_0 is read from V[:, 0], rho = 1).
 // Four rows per lane (16-byte loads for fp32); padded rows past n are masked.
-template <typename T, typename S>
-__global__ __launch_bounds__(BLOCK) void k_ls_update(int n, const T* __restrict__ p, T* __restrict__ q,
-                                                     S* __restrict__ V, long ldv, int j, State st,
-                                                     const double* __restrict__ dco) {
+// NT = 512 threads: the row grid is capped at MAX_BLOCKS blocks, and eight
+// waves per block fill the CUs' wave slots.
+template <typename T, typename S, int NT>
+__global__ __launch_bounds__(NT) void k_ls_update(int n, const T* __restrict__ p, T* __restrict__ q,
+                                                  S* __restrict__ V, long ldv, int j, State st,
+                                                  const double* __restrict__ dco) {
   const int flags = load_flags(st.hdr);  // tested after the coefficients are staged
   __shared__ T s_a[LS_MAX_RESTART + 1];
   __shared__ T s_d[LS_MAX_RESTART + 1];
-  for (int c = threadIdx.x; c <= j; c += BLOCK) {
+  for (int c = threadIdx.x; c <= j; c += NT) {
     s_a[c] = c < j ? (T)st.h2[c] : T(0);
     s_d[c] = (T)dco[c];
   }
@@ -346,7 +370,7 @@ __global__ __launch_bounds__(BLOCK) void k_ls_update(int n, const T* __restrict_
   const T dj = s_d[j];
   int r0, r1;
   block_rows(n, r0, r1);
-  for (int r = r0 + 4 * threadIdx.x; r < r1; r += 4 * BLOCK) {
+  for (int r = r0 + 4 * threadIdx.x; r < r1; r += 4 * NT) {
     const int nv = r1 - r < 4 ? r1 - r : 4;
     T pv[4], qv[4], sa[4] = {T(0), T(0), T(0), T(0)}, sd[4] = {T(0), T(0), T(0), T(0)};
     Quad<T, T>::load(p + r, pv);
