@@ -109,16 +109,24 @@ __device__ __forceinline__ T sell_row_cols(const Csr& A, const XF& xf, int s, in
 }
 
 // The entries whose loads go out together follow the slice's width K (a
-// wave-uniform value): 5 for rows of up to 5 entries, 7 up to 7, else 9 (a
-// 27-point row in three rounds; measured on the 27-point 128^3 system: SpMV +
-// projection 124 -> 119 us with 9 instead of 5, while a 5-point row loaded
-// in rounds of 9 wastes four loads per round and ran 5 % slower).
+// wave-uniform value): rounds of U in {5, 7, 9} entries, the U that loads the
+// fewest padded entries (ceil(K / U) U), the larger U on ties -- a 27-point
+// row in three rounds of 9, a 13-point one in two of 7, a 19-point one in
+// four of 5 (measured: 27-point 128^3 SpMV + projection 124 -> 119 us with 9
+// instead of 5; rounds of 9 on 5-, 13- and 19-entry rows, which load 4, 5
+// and 8 entries for nothing, ran 5-15 % slower).
+__device__ __forceinline__ int sell_round(int K) {
+  const int l5 = (K + 4) / 5 * 5, l7 = (K + 6) / 7 * 7, l9 = (K + 8) / 9 * 9;
+  return (l9 <= l7 && l9 <= l5) ? 9 : (l7 <= l5 ? 7 : 5);
+}
+
 template <typename T, bool D16, typename XF>
 __device__ __forceinline__ T sell_row_k(const Csr& A, const XF& xf, int s, int r, int lane) {
   const int base = A.sptr[s];
   const int K = (A.sptr[s + 1] - base) / SELL_C;
-  if (K <= 5) return sell_row_cols<T, D16, 5>(A, xf, s, r, lane, base, K);
-  if (K <= 7) return sell_row_cols<T, D16, 7>(A, xf, s, r, lane, base, K);
+  const int U = sell_round(K);
+  if (U == 5) return sell_row_cols<T, D16, 5>(A, xf, s, r, lane, base, K);
+  if (U == 7) return sell_row_cols<T, D16, 7>(A, xf, s, r, lane, base, K);
   return sell_row_cols<T, D16, 9>(A, xf, s, r, lane, base, K);
 }
 
