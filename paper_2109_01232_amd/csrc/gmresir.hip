@@ -750,8 +750,9 @@ struct Ctx {
   }
 
   void update_proj_dispatch(int k) {
-    // 16-byte basis loads: 2 fp64, 4 fp32 or 8 bf16 rows per lane
-    constexpr int R = 16 / sizeof(S);
+    // rows per lane: 16-byte loads of fp64 (2) and fp32 (4), 8-byte loads
+    // of bf16 (4: the pipelined steps hold two register sets)
+    constexpr int R = sizeof(S) == 2 ? 4 : 16 / sizeof(S);
     // an fp32 basis of 33..64 columns: eight waves (the grid is capped at
     // MAX_BLOCKS blocks; 27-point 128^3: 47.4 -> 45.3 us per launch); a bf16
     // basis keeps four (eight measured slower: 34.5 -> 45.0 us)

@@ -321,6 +321,18 @@ struct Packed<bf16_t, float, 8> {
   static __device__ __forceinline__ void hold(type& v) { asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w)); }
 };
 
+template <>
+struct Packed<bf16_t, float, 4> {
+  using type = uint2;
+  static __device__ __forceinline__ type load(const bf16_t* p) { return *(const uint2*)p; }
+  static __device__ __forceinline__ type zero() { return make_uint2(0u, 0u); }
+  static __device__ __forceinline__ float get(const type& v, int i) {
+    const uint32_t w = (i >> 1) == 0 ? v.x : v.y;
+    return __uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
+  }
+  static __device__ __forceinline__ void hold(type& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+};
+
 // 1 / ||w''|| of the previous iteration, the scale of the next basis vector:
 // summed from the partials k_update_norm left (nB > 0) in the order the
 // Givens step sums them (so both get the same bits), or read from the state
@@ -640,6 +652,98 @@ __device__ __forceinline__ void store_vec(T* p, const T (&v)[R]) {
   }
 }
 
+// x where keep holds, else +0 (also for NaN x: the padded rows past n are
+// never written), by a bit mask: a select fed by LDS reads is turned into a
+// branch by the compiler, and a branch makes its waits for memory inexact
+__device__ __forceinline__ float zero_unless(float x, bool keep) {
+  return __uint_as_float(__float_as_uint(x) & (keep ? 0xffffffffu : 0u));
+}
+
+// The steps of k_update_proj with the basis loads of step s + 1 issued
+// before the barrier of step s (two register sets used in turn), so they are
+// in flight while the block waits and finishes step s.  Every load is
+// unconditional, so the compiler's waits stay exact: lanes past the block's
+// rows and columns past k read a stand-in row of column 0 (h is zero past k,
+// rows past the range are masked where used, and no partial past k is kept);
+// w of a step is loaded before the next step's basis, so waiting for it
+// leaves those loads outstanding; the steps run in pairs (an odd count gets
+// one step with every row masked), so the loop has no conditional step.
+// Used for a bf16 basis (27-point 128^3: 35.5 -> 24.0 us per launch, 3.3 ->
+// 5.0 TB/s; 150^3 108.5 -> 73.9 us), with 4 rows (8 bytes) per lane so the
+// widest column classes keep both register sets without spills; fp32
+// measured the same either way, and fp64 would lose occupancy to the second
+// register set.
+template <typename T, typename S, int SLOTS, int R, int WV>
+__device__ __forceinline__ void update_proj_pipelined(int r0, int r1, const T* __restrict__ w_in, T* __restrict__ w_out,
+                                                      const S* __restrict__ V, long ldv, int k, const T (&hq)[SLOTS],
+                                                      T (&acc)[SLOTS], T (*s_part)[WV][WAVE * R], int lane, int wid) {
+  constexpr int STEP = WAVE * R;
+  using P = Packed<S, T, R>;
+  using VR = typename P::type[SLOTS];
+  // stand-in row, 64-aligned: below n whenever the range is not empty (only
+  // then are w and the steps touched); an empty range (r0 = n) makes just the
+  // first basis load below, which stays inside V's m + 1 >= 2 columns
+  const int rz = r0 & ~63;
+  auto load_step = [&](int base, VR& dst) {
+    const int r = base + R * lane;
+    const bool rows_ok = r1 - r > 0;
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+      const int c = wid + WV * q;
+      dst[q] = P::load(c < k && rows_ok ? V + (size_t)c * ldv + r : V + rz);
+    }
+  };
+  auto step = [&](int base, int buf, VR& vr, VR& vn) {
+    const int r = base + R * lane;
+    const int nv = r1 - r;
+    T wv[R];
+    load_vec<T, R>(w_in + (nv > 0 ? r : rz), wv);
+    T sp[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) sp[i] = T(0);
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q)
+#pragma unroll
+      for (int i = 0; i < R; ++i) sp[i] += hq[q] * ((i < nv) ? P::get(vr[q], i) : T(0));
+#pragma unroll
+    for (int i = 0; i < R; ++i) s_part[buf][wid][R * lane + i] = sp[i];
+    load_step(base + STEP, vn);  // past r1 every lane reads the stand-in row (unused)
+    // an LDS-only barrier: the basis loads just issued stay in flight
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) P::hold(vr[q]);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int e = R * lane + i;
+      T t = (s_part[buf][0][e] + s_part[buf][1][e]) + (s_part[buf][2][e] + s_part[buf][3][e]);
+      if constexpr (WV == 8) t += (s_part[buf][4][e] + s_part[buf][5][e]) + (s_part[buf][6][e] + s_part[buf][7][e]);
+      wv[i] = zero_unless(wv[i] - t, i < nv);
+    }
+    if (wid == 0 && nv > 0) {
+      if (nv >= R) {
+        store_vec<T, R>(w_out + r, wv);
+      } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+          if (i < nv) w_out[r + i] = wv[i];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q)
+#pragma unroll
+      for (int i = 0; i < R; ++i) acc[q] += ((i < nv) ? P::get(vr[q], i) : T(0)) * wv[i];
+  };
+  VR va, vb;
+  const int npairs = (r1 - r0 + 2 * STEP - 1) / (2 * STEP);
+  load_step(r0, va);
+  for (int p = 0; p < npairs; ++p) {
+    step(r0 + 2 * p * STEP, 0, va, vb);
+    step(r0 + (2 * p + 1) * STEP, 1, vb, va);
+  }
+}
+
 // The block's WV waves (4 or 8) share rows and split the columns: wave w
 // holds columns c = w + WV q (q < SLOTS) of R rows per lane in registers.
 // Per step of 64 R rows: each wave forms its part of (V h1)[r] over its
@@ -674,66 +778,70 @@ __global__ __launch_bounds__(WV * WAVE) void k_update_proj(int n, const T* __res
   }
   int r0, r1;
   block_rows(n, r0, r1);
-  int buf = 0;
-  for (int base = r0; base < r1; base += STEP, buf ^= 1) {
-    const int r = base + R * lane;
-    const int nv = r1 - r;  // rows of this lane inside the block's range (may be <= 0 or > R)
-    using P = Packed<S, T, R>;
-    typename P::type vr[SLOTS];
-    T s[R];
-    // narrow bases: w's load goes out with V's, before the barrier (with few
-    // columns the step is otherwise two dependent memory round trips); wide
-    // ones load it after the barrier to keep registers for V
-    constexpr bool W_EARLY = SLOTS <= 4;
-    T wv[R];
-    if constexpr (W_EARLY) {
-      if (nv > 0) {
-        load_vec<T, R>(w_in + r, wv);
-      } else {
+  if constexpr (sizeof(S) == 2) {
+    update_proj_pipelined<T, S, SLOTS, R, WV>(r0, r1, w_in, w_out, V, ldv, k, hq, acc, s_part, lane, wid);
+  } else {
+    int buf = 0;
+    for (int base = r0; base < r1; base += STEP, buf ^= 1) {
+      const int r = base + R * lane;
+      const int nv = r1 - r;  // rows of this lane inside the block's range (may be <= 0 or > R)
+      using P = Packed<S, T, R>;
+      typename P::type vr[SLOTS];
+      T s[R];
+      // narrow bases: w's load goes out with V's, before the barrier (with few
+      // columns the step is otherwise two dependent memory round trips); wide
+      // ones load it after the barrier to keep registers for V
+      constexpr bool W_EARLY = SLOTS <= 4;
+      T wv[R];
+      if constexpr (W_EARLY) {
+        if (nv > 0) {
+          load_vec<T, R>(w_in + r, wv);
+        } else {
 #pragma unroll
-        for (int i = 0; i < R; ++i) wv[i] = T(0);
+          for (int i = 0; i < R; ++i) wv[i] = T(0);
+        }
       }
-    }
 #pragma unroll
-    for (int i = 0; i < R; ++i) s[i] = T(0);
+      for (int i = 0; i < R; ++i) s[i] = T(0);
 #pragma unroll
-    for (int q = 0; q < SLOTS; ++q) {
-      const int c = wid + WV * q;
-      vr[q] = (c < k && nv > 0) ? P::load(V + (size_t)c * ldv + r) : P::zero();
+      for (int q = 0; q < SLOTS; ++q) {
+        const int c = wid + WV * q;
+        vr[q] = (c < k && nv > 0) ? P::load(V + (size_t)c * ldv + r) : P::zero();
 #pragma unroll
-      for (int i = 0; i < R; ++i) s[i] += hq[q] * ((i < nv) ? P::get(vr[q], i) : T(0));
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) s_part[buf][wid][R * lane + i] = s[i];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < SLOTS; ++q) P::hold(vr[q]);
-    if constexpr (!W_EARLY) {
-      if (nv > 0) {
-        load_vec<T, R>(w_in + r, wv);
-      } else {
-#pragma unroll
-        for (int i = 0; i < R; ++i) wv[i] = T(0);
+        for (int i = 0; i < R; ++i) s[i] += hq[q] * ((i < nv) ? P::get(vr[q], i) : T(0));
       }
-    }
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int e = R * lane + i;
-      T t = (s_part[buf][0][e] + s_part[buf][1][e]) + (s_part[buf][2][e] + s_part[buf][3][e]);
-      if constexpr (WV == 8) t += (s_part[buf][4][e] + s_part[buf][5][e]) + (s_part[buf][6][e] + s_part[buf][7][e]);
-      wv[i] = (i < nv) ? wv[i] - t : T(0);
-    }
-    if (wid == 0 && nv > 0) {
-      if (nv >= R) {
-        store_vec<T, R>(w_out + r, wv);
-      } else {
-        for (int i = 0; i < nv; ++i) w_out[r + i] = wv[i];
+      for (int i = 0; i < R; ++i) s_part[buf][wid][R * lane + i] = s[i];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q) P::hold(vr[q]);
+      if constexpr (!W_EARLY) {
+        if (nv > 0) {
+          load_vec<T, R>(w_in + r, wv);
+        } else {
+#pragma unroll
+          for (int i = 0; i < R; ++i) wv[i] = T(0);
+        }
       }
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int e = R * lane + i;
+        T t = (s_part[buf][0][e] + s_part[buf][1][e]) + (s_part[buf][2][e] + s_part[buf][3][e]);
+        if constexpr (WV == 8) t += (s_part[buf][4][e] + s_part[buf][5][e]) + (s_part[buf][6][e] + s_part[buf][7][e]);
+        wv[i] = (i < nv) ? wv[i] - t : T(0);
+      }
+      if (wid == 0 && nv > 0) {
+        if (nv >= R) {
+          store_vec<T, R>(w_out + r, wv);
+        } else {
+          for (int i = 0; i < nv; ++i) w_out[r + i] = wv[i];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q)
+#pragma unroll
+        for (int i = 0; i < R; ++i) acc[q] += ((i < nv) ? P::get(vr[q], i) : T(0)) * wv[i];
     }
-#pragma unroll
-    for (int q = 0; q < SLOTS; ++q)
-#pragma unroll
-      for (int i = 0; i < R; ++i) acc[q] += ((i < nv) ? P::get(vr[q], i) : T(0)) * wv[i];
   }
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q) {
