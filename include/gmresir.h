@@ -137,10 +137,16 @@ size_t gmresir_matrix_storage_bytes(int64_t n, int64_t nnz);
    owned by the caller and written here.  The row pointers are copied to the
    host once to cut the rows into tiles of at most 512 rows / 2560 nonzeros.
    When no row has more than 512 nonzeros and the padding stays bounded, a
-   sliced ELLPACK copy (slices of 64 rows, one row per lane) is built too; its
-   column indices are 16-bit offsets from the row when every entry lies within
-   32767 columns of its row (the SpMV then reads 6 bytes per fp32 nonzero
-   instead of 8), else 32-bit indices.  Errors: INVALID_ARG (null pointer, n < 1, nnz < 0, nnz >= 2^31, rowptr not
+   sliced ELLPACK copy (slices of 64 rows, one row per lane) is built too.
+   When the rows of every slice share their column offsets c - r (stencils:
+   each slice's sorted union of offsets is at most 1.25 times as many slots
+   as its longest row gives; every row's columns strictly increasing), the
+   copy keeps one offset list per slice and zeros for absent entries, and the
+   SpMV reads only the values (4 bytes per fp32 slot, no row lengths).
+   Otherwise its column indices are 16-bit offsets from the row when every
+   entry lies within 32767 columns of its row (the SpMV then reads 6 bytes per
+   fp32 nonzero instead of 8), else 32-bit indices.  colidx is copied to the
+   host once to build the offset lists.  Errors: INVALID_ARG (null pointer, n < 1, nnz < 0, nnz >= 2^31, rowptr not
    monotone or rowptr[n] != nnz), WORKSPACE (storage too small), HIP. */
 int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
                           const double* vals, void* storage, size_t storage_bytes, void* stream,
@@ -151,7 +157,8 @@ int64_t gmresir_matrix_nnz(const gmresir_matrix* A);
 int64_t gmresir_matrix_tiles(const gmresir_matrix* A);
 /* Layout the SpMV kernels read: 0 = row tiles of the CSR arrays only,
    1 = sliced ELLPACK copy with 32-bit columns, 2 = sliced copy with 16-bit
-   column offsets; -1 for A == NULL. */
+   column offsets, 3 = sliced copy with one offset list per slice; -1 for
+   A == NULL. */
 int32_t gmresir_matrix_layout(const gmresir_matrix* A);
 
 /* y = A x (Algorithm 1, the SpMV).  prec GMRESIR_FP64: x, y fp64 and the fp64

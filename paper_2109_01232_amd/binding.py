@@ -240,7 +240,8 @@ class Matrix:
     @property
     def layout(self) -> int:
         """0 = CSR row tiles only, 1 = sliced ELLPACK with 32-bit columns,
-        2 = sliced ELLPACK with 16-bit column offsets."""
+        2 = sliced ELLPACK with 16-bit column offsets, 3 = sliced ELLPACK with
+        one column-offset list per slice."""
         return int(lib().gmresir_matrix_layout(self.handle))
 
     def close(self):

@@ -137,6 +137,9 @@ struct Csr {
   const int* scol;      // column of each entry (d16 == 0)
   const short* scol16;  // column - row of each entry (d16 != 0; padding 0, rows >= n relative to row 0)
   int d16;
+  // shared != 0: one list of column offsets per slice (sorted, at scol +
+  // sptr[s] / 64), the same for all its rows; absent entries hold value 0
+  int shared;
   const void* svals;  // element type MT, like vals
 };
 

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <iterator>
 #include <map>
 #include <tuple>
 #include <mutex>
@@ -39,8 +40,10 @@ struct gmresir_matrix {
   bool sell;
   int nslices;
   int32_t* sell_ptr;
-  int32_t* sell_col;  // 32-bit columns, or (sell_d16) 16-bit offsets from the row in the same region
+  int32_t* sell_col;  // 32-bit columns, or (sell_d16) 16-bit offsets from the row in the same region,
+                      // or (sell_shared) each slice's shared offsets at sell_ptr[s] / 64
   bool sell_d16;
+  bool sell_shared;
   float* sell_v32;
   double* sell_v64;
   int device;
@@ -133,6 +136,7 @@ Csr csr_of(const gmresir_matrix* A, bool fp64) {
   c.scol = A->sell_col;
   c.scol16 = (const short*)A->sell_col;
   c.d16 = A->sell_d16 ? 1 : 0;
+  c.shared = A->sell_shared ? 1 : 0;
   c.svals = fp64 ? (const void*)A->sell_v64 : (const void*)A->sell_v32;
   return c;
 }
@@ -1508,13 +1512,58 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
     else sptr[sl + 1] = (int32_t)next;
   }
   const size_t E = (size_t)sell_max_entries(n, nnz);
+  // shared offsets: per slice the sorted union of its rows' offsets c - r,
+  // taken when every row's columns strictly increase and the slots grow by
+  // at most SHARED_MAX_GROWTH over the per-row copy (rows mostly repeat the
+  // previous row's offsets, so the union is merged only on a change)
+  bool shared = false;
+  std::vector<int32_t> sptr3, soff;
+  if (sell) {
+    std::vector<int32_t> ci(nnz);
+    HIP_TRY(hipMemcpyAsync(ci.data(), colidx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    sptr3.assign(ns + 1, 0);
+    std::vector<int32_t> U, row, prev, merged;
+    bool ok = true;
+    for (int64_t sl = 0; sl < ns && ok; ++sl) {
+      U.clear();
+      prev.clear();
+      for (int64_t r = sl * SELL_C; r < std::min<int64_t>(n, (sl + 1) * SELL_C) && ok; ++r) {
+        row.clear();
+        for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
+          const int32_t d = ci[p] - (int32_t)r;
+          if (!row.empty() && d <= row.back()) {
+            ok = false;
+            break;
+          }
+          row.push_back(d);
+        }
+        if (!ok || row == prev) continue;
+        merged.clear();
+        std::set_union(U.begin(), U.end(), row.begin(), row.end(), std::back_inserter(merged));
+        U.swap(merged);
+        prev = row;
+      }
+      if ((int64_t)U.size() > SELL_MAX_ROW) ok = false;
+      if (!ok) break;
+      soff.insert(soff.end(), U.begin(), U.end());
+      sptr3[sl + 1] = sptr3[sl] + SELL_C * (int32_t)U.size();
+    }
+    shared = ok && (size_t)sptr3[ns] <= E && (double)sptr3[ns] <= SHARED_MAX_GROWTH * (double)sptr[ns];
+  }
   char* sbase = st + align_up((size_t)nnz * 4) + align_up((size_t)(max_tiles(n, nnz) + 1) * 4);
   int32_t* d_sptr = (int32_t*)sbase;
   int32_t* d_scol = (int32_t*)(sbase + align_up((ns + 1) * 4));
   float* d_sv32 = (float*)((char*)d_scol + align_up(E * 4));
   double* d_sv64 = (double*)((char*)d_sv32 + align_up(E * 4));
   bool d16 = false;
-  if (sell) {
+  if (shared) {
+    HIP_TRY(hipMemcpyAsync(d_sptr, sptr3.data(), (ns + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_scol, soff.data(), soff.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_build_sell_shared, dim3((unsigned)ns), dim3(SELL_C), 0, s, (int)n, rowptr, colidx, vals,
+                       d_sptr, d_scol, d_sv32, d_sv64);
+    HIP_TRY(hipGetLastError());
+  } else if (sell) {
     // 16-bit column offsets if every entry is within 32767 columns of its row
     // (the check's flag sits in the column region until the copy is built)
     int far = 1;
@@ -1537,6 +1586,7 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
   A->sell_ptr = d_sptr;
   A->sell_col = d_scol;
   A->sell_d16 = d16;
+  A->sell_shared = shared;
   A->sell_v32 = d_sv32;
   A->sell_v64 = d_sv64;
   A->n = n;
@@ -1562,7 +1612,9 @@ int gmresir_matrix_destroy(gmresir_matrix* A) {
 int64_t gmresir_matrix_n(const gmresir_matrix* A) { return A ? A->n : -1; }
 int64_t gmresir_matrix_nnz(const gmresir_matrix* A) { return A ? A->nnz : -1; }
 int64_t gmresir_matrix_tiles(const gmresir_matrix* A) { return A ? A->ntiles : -1; }
-int32_t gmresir_matrix_layout(const gmresir_matrix* A) { return A ? (A->sell ? (A->sell_d16 ? 2 : 1) : 0) : -1; }
+int32_t gmresir_matrix_layout(const gmresir_matrix* A) {
+  return A ? (A->sell ? (A->sell_shared ? 3 : A->sell_d16 ? 2 : 1) : 0) : -1;
+}
 
 int gmresir_spmv(const gmresir_matrix* A, int32_t prec, const void* x, void* y, void* stream) {
   if (!A || !x || !y) {

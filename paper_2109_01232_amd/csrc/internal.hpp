@@ -29,10 +29,16 @@ constexpr int SPMV_UNROLL = 5;  // nonzeros per thread whose loads are issued to
 // of row 64 s + l at sell_ptr[s] + 64 k + l; padding entries point at the row
 // itself with value 0 and are skipped by the row length.  Built when no row
 // is longer than SELL_MAX_ROW and the padded size fits sell_max_entries;
-// otherwise the row-tiled CSR kernels run.
+// otherwise the row-tiled CSR kernels run.  When the rows of each slice share
+// their column offsets (stencils: the union of a slice's offsets is hardly
+// wider than its longest row), slot k of slice s holds offset
+// sell_col[sell_ptr[s] / 64 + k] for all 64 rows, absent entries value 0: no
+// column index and no row length is read per entry (SHARED_MAX_GROWTH bounds
+// the extra slots against the per-row copy).
 constexpr int SELL_C = 64;
 constexpr int SELL_MAX_ROW = 512;
 inline int64_t sell_max_entries(int64_t n, int64_t nnz) { return nnz + nnz / 4 + (n < 4096 ? n : 4096) * 4; }
+constexpr double SHARED_MAX_GROWTH = 1.25;
 
 // Upper bound of the number of tiles (every tile holds at least one row).
 inline int64_t max_tiles(int64_t n, int64_t nnz) {

@@ -79,13 +79,18 @@ __device__ __forceinline__ void stage_products(const Csr& A, int p0, int len, co
 // owns it (the same order, and so the same bits, as the tiled CSR kernels).
 // Loads of U entries are issued before their gathers; padding entries past
 // the row length are loaded (valid addresses) but not added.
-// D16: the columns are 16-bit offsets from the row (rows past n: from row 0).
-template <typename T, bool D16, int U, typename XF>
+// LAYOUT 1: 32-bit columns; 2: 16-bit offsets from the row (rows past n: from
+// row 0); 3: the slice's shared offsets (a wave-uniform load), every slot
+// added -- an absent entry adds 0 * x[c] = +-0 to a sum that started at +0,
+// which leaves it unchanged (x finite), so the bits match the CSR row sum --
+// and the gathered index clamped to [0, n) (absent neighbours, rows past n).
+template <typename T, int LAYOUT, int U, typename XF>
 __device__ __forceinline__ T sell_row_cols(const Csr& A, const XF& xf, int s, int r, int lane, int base, int K) {
 #pragma clang fp contract(off)
   const T* vals = (const T*)A.svals;
-  const int len = r < A.n ? A.rowptr[r + 1] - A.rowptr[r] : 0;
+  const int len = LAYOUT == 3 ? K : (r < A.n ? A.rowptr[r + 1] - A.rowptr[r] : 0);
   const int rr = r < A.n ? r : 0;
+  const int* soff = A.scol + base / SELL_C;
   T sum = T(0);
   for (int k0 = 0; k0 < K; k0 += U) {
     int cc[U];
@@ -93,7 +98,8 @@ __device__ __forceinline__ T sell_row_cols(const Csr& A, const XF& xf, int s, in
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u < K ? k0 + u : K - 1;
-      if constexpr (D16) cc[u] = rr + (int)A.scol16[base + SELL_C * k + lane];
+      if constexpr (LAYOUT == 3) cc[u] = min(max(r + soff[k], 0), A.n - 1);
+      else if constexpr (LAYOUT == 2) cc[u] = rr + (int)A.scol16[base + SELL_C * k + lane];
       else cc[u] = A.scol[base + SELL_C * k + lane];
       vv[u] = vals[base + SELL_C * k + lane];
     }
@@ -120,21 +126,23 @@ __device__ __forceinline__ int sell_round(int K) {
   return (l9 <= l7 && l9 <= l5) ? 9 : (l7 <= l5 ? 7 : 5);
 }
 
-template <typename T, bool D16, typename XF>
+template <typename T, int LAYOUT, typename XF>
 __device__ __forceinline__ T sell_row_k(const Csr& A, const XF& xf, int s, int r, int lane) {
   const int base = A.sptr[s];
   const int K = (A.sptr[s + 1] - base) / SELL_C;
   const int U = sell_round(K);
-  if (U == 5) return sell_row_cols<T, D16, 5>(A, xf, s, r, lane, base, K);
-  if (U == 7) return sell_row_cols<T, D16, 7>(A, xf, s, r, lane, base, K);
-  return sell_row_cols<T, D16, 9>(A, xf, s, r, lane, base, K);
+  if (U == 5) return sell_row_cols<T, LAYOUT, 5>(A, xf, s, r, lane, base, K);
+  if (U == 7) return sell_row_cols<T, LAYOUT, 7>(A, xf, s, r, lane, base, K);
+  return sell_row_cols<T, LAYOUT, 9>(A, xf, s, r, lane, base, K);
 }
 
-// The column width is chosen once per slice (a wave-uniform branch), not per
-// load: a load under a branch is waited for at the branch's end.
+// The layout and the round size are chosen once per slice (wave-uniform
+// branches), not per load: a load under a branch is waited for at the
+// branch's end.
 template <typename T, typename XF>
 __device__ __forceinline__ T sell_row(const Csr& A, const XF& xf, int s, int r, int lane) {
-  return A.d16 ? sell_row_k<T, true>(A, xf, s, r, lane) : sell_row_k<T, false>(A, xf, s, r, lane);
+  if (A.shared) return sell_row_k<T, 3>(A, xf, s, r, lane);
+  return A.d16 ? sell_row_k<T, 2>(A, xf, s, r, lane) : sell_row_k<T, 1>(A, xf, s, r, lane);
 }
 
 // SpMV over the sliced ELLPACK copy: the block takes a contiguous range of
@@ -1643,6 +1651,32 @@ __global__ void k_build_sell(int n, const int* __restrict__ rowptr, const int* _
     }
     if (d16) scol16[e] = (short)(c - rr);
     else scol[e] = c;
+    sv64[e] = v;
+    sv32[e] = (float)v;
+  }
+}
+
+// Values of the shared-offset sliced copy (one block of 64 threads per
+// slice, one row per thread): slot k of the row takes the CSR entry at column
+// r + soff[k] if the row has one, else 0; fp32 values rounded to nearest even
+// like the CSR copy.  The host has checked that every row's columns strictly
+// increase and lie in its slice's offset list, so one pass with a cursor
+// takes every entry.
+__global__ void k_build_sell_shared(int n, const int* __restrict__ rowptr, const int* __restrict__ colidx,
+                                    const double* __restrict__ vals, const int* __restrict__ sptr,
+                                    const int* __restrict__ soff_all, float* __restrict__ sv32,
+                                    double* __restrict__ sv64) {
+  const int sl = blockIdx.x, lane = threadIdx.x;
+  const int r = sl * SELL_C + lane;
+  const int base = sptr[sl];
+  const int K = (sptr[sl + 1] - base) / SELL_C;
+  const int* soff = soff_all + base / SELL_C;
+  int p = r < n ? rowptr[r] : 0;
+  const int pe = r < n ? rowptr[r + 1] : 0;
+  for (int k = 0; k < K; ++k) {
+    double v = 0.0;
+    if (p < pe && colidx[p] - r == soff[k]) v = vals[p++];
+    const int e = base + SELL_C * k + lane;
     sv64[e] = v;
     sv32[e] = (float)v;
   }

@@ -82,17 +82,24 @@ def long_row_matrix(n=8000, seed=1):
     return P.CSR(n, np.array(rowptr, dtype=np.int32), np.concatenate(cols).astype(np.int32), np.concatenate(vals))
 
 
-def far_column_matrix(side=264, seed=2):
+def far_column_matrix(side=264, seed=2, far=True):
     """2D convection-diffusion on side^2 >= 65473 rows (enough slices for the
-    sliced SpMV + projection kernel) plus one coupling per seventh row to the
-    row n/2 away: columns too far from their rows for 16-bit offsets, so the
-    sliced copy keeps 32-bit columns.  Still diagonally dominant."""
+    sliced SpMV + projection kernel) plus one coupling per seventh row, each
+    at its own distance (so the rows of a slice do not share their column
+    offsets): far=True about n/2 away, too far for 16-bit offsets, so the
+    sliced copy keeps 32-bit columns; far=False 100..3000 columns away, so it
+    keeps 16-bit offsets.  Still diagonally dominant."""
     import scipy.sparse as sp
     A0 = P.conv_diff(2, side, 20.0, (1.0, 0.3))
     n = A0.n
     rng = np.random.default_rng(seed)
     r = np.arange(0, n, 7)
-    S = A0.scipy() + sp.csr_matrix((-1e-3 * rng.uniform(0.5, 1.0, len(r)), (r, (r + n // 2) % n)), shape=(n, n))
+    if far:
+        c = (r + n // 2 + rng.integers(-1000, 1000, len(r))) % n
+    else:
+        d = rng.choice([-1, 1], len(r)) * rng.integers(100, 3000, len(r))
+        c = np.where((r + d < 0) | (r + d >= n), r - d, r + d)
+    S = A0.scipy() + sp.csr_matrix((-1e-3 * rng.uniform(0.5, 1.0, len(r)), (r, c)), shape=(n, n))
     S = S.tocsr()
     S.sort_indices()
     return P.CSR(n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data), S
@@ -102,12 +109,15 @@ def far_column_matrix(side=264, seed=2):
 # SpMV
 # ---------------------------------------------------------------------------
 
-# layout the library picks: 2 = sliced copy with 16-bit column offsets, 1 = with
-# 32-bit columns, 0 = CSR row tiles only (a row longer than 512)
-SPMV_LAYOUT = {"cfg1": 2, "ragged2d": 2, "aniso3d": 2, "varcoef27": 2, "irregular": 0, "longrow": 0, "farcols": 1}
+# layout the library picks: 3 = sliced copy with one column-offset list per
+# slice (stencils), 2 = with 16-bit column offsets per entry, 1 = with 32-bit
+# columns, 0 = CSR row tiles only (a row longer than 512)
+SPMV_LAYOUT = {"cfg1": 3, "ragged2d": 3, "aniso3d": 3, "varcoef27": 3, "irregular": 0, "longrow": 0, "farcols": 1,
+               "nearcols": 2}
 
 
-@pytest.mark.parametrize("case", ["cfg1", "ragged2d", "aniso3d", "varcoef27", "irregular", "longrow", "farcols"])
+@pytest.mark.parametrize("case", ["cfg1", "ragged2d", "aniso3d", "varcoef27", "irregular", "longrow", "farcols",
+                                  "nearcols"])
 def test_spmv_parity(case):
     say("spmv", case)
     if case == "cfg1":
@@ -122,6 +132,8 @@ def test_spmv_parity(case):
         A = ragged_matrix_with_long_row()
     elif case == "farcols":
         A, _ = far_column_matrix()
+    elif case == "nearcols":
+        A, _ = far_column_matrix(far=False)
     else:
         A = long_row_matrix()
     M = B.Matrix.from_csr(A)
@@ -366,18 +378,21 @@ def test_row_tiled_path_solve():
         assert np.linalg.norm(bb - S @ x.cpu().numpy()) / np.linalg.norm(bb) <= 1e-10
 
 
-def test_far_column_solve():
-    """Columns beyond the 16-bit offset range keep the sliced copy on 32-bit
-    columns; at 69696 rows the fused SpMV + projection runs its sliced kernel
-    on them.  First cycle against the oracle's, then the fp64 residual."""
-    A, S = far_column_matrix()
+@pytest.mark.parametrize("far", [True, False])
+def test_far_column_solve(far):
+    """Rows of a slice that do not share their column offsets keep the
+    per-entry sliced copy -- 32-bit columns beyond the 16-bit offset range
+    (far), 16-bit offsets otherwise; at 69696 rows the fused SpMV +
+    projection runs its sliced kernel on them.  First cycle against the
+    oracle's, then the fp64 residual."""
+    A, S = far_column_matrix(far=far)
     u = np.random.default_rng(12).uniform(-1, 1, A.n)
     bb = S @ u
     M = B.Matrix.from_csr(A)
-    assert M.layout == 1
+    assert M.layout == (1 if far else 2)
     b = dev_tensor(bb)
     for inner in ("fp32", "fp64"):
-        say("far-column solve", inner)
+        say("far-column solve", far, inner)
         x, d, h = B.solve(M, b, restart=30, inner=inner, rtol=1e-10, check_mode=0, hist_cap=20000)
         ref = (L.gmres(A, bb, m=30, rtol=1e-10, check_mode=0, max_iters=30) if inner == "fp64" else
                L.gmres_ir(A, bb, m=30, rtol=1e-10, inner="fp32", check_mode=0, max_iters=30))
