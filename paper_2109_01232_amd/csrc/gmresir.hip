@@ -44,6 +44,7 @@ struct gmresir_matrix {
                       // or (sell_shared) each slice's shared offsets at sell_ptr[s] / 64
   bool sell_d16;
   bool sell_shared;
+  bool sell_wide;  // shared offsets and some slice wider than 9: the kernels' wide-round instances
   float* sell_v32;
   double* sell_v64;
   int device;
@@ -694,7 +695,8 @@ struct Ctx {
       bool done = false;
       if constexpr (KMAX == 64 || KMAX == 128) {
         if (A->nnz > 6 * A->n) {
-          auto kern = k_spmv_proj_sell<T, S, KMAX / (2 * NWAVES), SCALED, 2 * NWAVES>;
+          auto kern = A->sell_wide ? k_spmv_proj_sell<T, S, KMAX / (2 * NWAVES), SCALED, 2 * NWAVES, true>
+                                   : k_spmv_proj_sell<T, S, KMAX / (2 * NWAVES), SCALED, 2 * NWAVES, false>;
           g = std::max(1, std::min(resident_grid((const void*)kern, 0, 2 * NWAVES * WAVE), (A->nslices + SPS - 1) / SPS));
           prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(2 * NWAVES * WAVE), 0, stream, Ain, src, V, L.ldv,
                        j, w1, st, part, (const T*)norm_part(), nB);
@@ -702,7 +704,8 @@ struct Ctx {
         }
       }
       if (!done) {
-        auto kern = k_spmv_proj_sell<T, S, KMAX / NW, SCALED, NW>;
+        auto kern = A->sell_wide ? k_spmv_proj_sell<T, S, KMAX / NW, SCALED, NW, true>
+                                 : k_spmv_proj_sell<T, S, KMAX / NW, SCALED, NW, false>;
         g = std::max(1, std::min(resident_grid((const void*)kern, 0, NW * WAVE), (A->nslices + SPS - 1) / SPS));
         prof->launch(GMRESIR_CAT_SPMV_PROJ, b, kern, dim3(g), dim3(NW * WAVE), 0, stream, Ain, src, V, L.ldv, j, w1,
                      st, part, (const T*)norm_part(), nB);
@@ -843,7 +846,8 @@ struct Ctx {
 
   template <int SLOTS, int NW, bool SCALED>
   void ls_spmv_dots_sell_launch(const T* gsrc, const T* own, int j, bool own_read) {
-    auto kern = k_ls_spmv_dots_sell<T, S, SLOTS, SCALED, NW>;
+    auto kern = A->sell_wide ? k_ls_spmv_dots_sell<T, S, SLOTS, SCALED, NW, true>
+                             : k_ls_spmv_dots_sell<T, S, SLOTS, SCALED, NW, false>;
     constexpr int SPS = (sizeof(T) == 8 ? TILE_ROWS : 2 * TILE_ROWS) / SELL_C;  // slices per stage
     const int g = std::max(1, std::min(resident_grid((const void*)kern, 0, NW * WAVE), (A->nslices + SPS - 1) / SPS));
     const double b = spmv_bytes() + 2.0 * sT() * n + sS() * n * j + (SCALED ? sS() * n : own_read ? sT() * n : 0.0);
@@ -1551,6 +1555,9 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
     }
     shared = ok && (size_t)sptr3[ns] <= E && (double)sptr3[ns] <= SHARED_MAX_GROWTH * (double)sptr[ns];
   }
+  bool wide = false;
+  if (shared)
+    for (int64_t sl = 0; sl < ns && !wide; ++sl) wide = sptr3[sl + 1] - sptr3[sl] > 9 * SELL_C;
   char* sbase = st + align_up((size_t)nnz * 4) + align_up((size_t)(max_tiles(n, nnz) + 1) * 4);
   int32_t* d_sptr = (int32_t*)sbase;
   int32_t* d_scol = (int32_t*)(sbase + align_up((ns + 1) * 4));
@@ -1587,6 +1594,7 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
   A->sell_col = d_scol;
   A->sell_d16 = d16;
   A->sell_shared = shared;
+  A->sell_wide = wide;
   A->sell_v32 = d_sv32;
   A->sell_v64 = d_sv64;
   A->n = n;
@@ -1627,12 +1635,12 @@ int gmresir_spmv(const gmresir_matrix* A, int32_t prec, const void* x, void* y, 
   }
   hipStream_t s = (hipStream_t)stream;
   if (prec == GMRESIR_FP64) {
-    auto kern = k_spmv<double>;
+    auto kern = A->sell_wide ? k_spmv<double, true> : k_spmv<double, false>;
     const size_t smem = A->sell ? 0 : (size_t)A->lds_nnz * sizeof(double);
     int g = grid_spmv(A);
     hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), smem, s, csr_of(A, true), (const double*)x, (double*)y);
   } else if (prec == GMRESIR_FP32) {
-    auto kern = k_spmv<float>;
+    auto kern = A->sell_wide ? k_spmv<float, true> : k_spmv<float, false>;
     const size_t smem = A->sell ? 0 : (size_t)A->lds_nnz * sizeof(float);
     int g = grid_spmv(A);
     hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), smem, s, csr_of(A, false), (const float*)x, (float*)y);

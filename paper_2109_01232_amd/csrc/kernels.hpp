@@ -126,15 +126,17 @@ __device__ __forceinline__ int sell_round(int K) {
   return (l9 <= l7 && l9 <= l5) ? 9 : (l7 <= l5 ? 7 : 5);
 }
 
-template <typename T, int LAYOUT, typename XF>
+template <typename T, int LAYOUT, bool WIDE, typename XF>
 __device__ __forceinline__ T sell_row_k(const Csr& A, const XF& xf, int s, int r, int lane) {
   const int base = A.sptr[s];
   const int K = (A.sptr[s + 1] - base) / SELL_C;
-  // shared offsets: no index registers per entry, so a slice 10..27 wide
-  // issues all its loads in one round (27-point 128^3 SpMV + projection 94 ->
-  // 93 us fp32, 76 -> 69 us with a bf16 basis, against rounds of 9; 19-point
-  // fp64 SpMV 77 -> 73 us)
-  if constexpr (LAYOUT == 3) {
+  // WIDE (shared offsets, slices wider than 9): no index registers per entry,
+  // so a slice 10..27 wide issues all its loads in one round (27-point 128^3
+  // SpMV + projection 94 -> 93 us fp32, 76 -> 69 us with a bf16 basis, against
+  // rounds of 9; 19-point fp64 SpMV 77 -> 73 us).  A template choice: the
+  // wide rounds' registers would cost the narrow stencils occupancy (7-point
+  // 150^3 one-reduction SpMV 184 -> 221 us when compiled in).
+  if constexpr (LAYOUT == 3 && WIDE) {
     if (K > 9 && K <= 14) return sell_row_cols<T, LAYOUT, 14>(A, xf, s, r, lane, base, K);
     if (K > 14 && K <= 19) return sell_row_cols<T, LAYOUT, 19>(A, xf, s, r, lane, base, K);
     if (K > 19 && K <= 27) return sell_row_cols<T, LAYOUT, 27>(A, xf, s, r, lane, base, K);
@@ -148,16 +150,16 @@ __device__ __forceinline__ T sell_row_k(const Csr& A, const XF& xf, int s, int r
 // The layout and the round size are chosen once per slice (wave-uniform
 // branches), not per load: a load under a branch is waited for at the
 // branch's end.
-template <typename T, typename XF>
+template <typename T, bool WIDE = false, typename XF>
 __device__ __forceinline__ T sell_row(const Csr& A, const XF& xf, int s, int r, int lane) {
-  if (A.shared) return sell_row_k<T, 3>(A, xf, s, r, lane);
-  return A.d16 ? sell_row_k<T, 2>(A, xf, s, r, lane) : sell_row_k<T, 1>(A, xf, s, r, lane);
+  if (A.shared) return sell_row_k<T, 3, WIDE>(A, xf, s, r, lane);
+  return A.d16 ? sell_row_k<T, 2, false>(A, xf, s, r, lane) : sell_row_k<T, 1, false>(A, xf, s, r, lane);
 }
 
 // SpMV over the sliced ELLPACK copy: the block takes a contiguous range of
 // slices, its waves take every fourth of them, each lane one row; epi(r, y)
 // per row as in spmv_tiles.
-template <typename T, typename XF, typename EPI>
+template <typename T, bool WIDE = false, typename XF, typename EPI>
 __device__ __forceinline__ void sell_rows(const Csr& A, const XF& xf, EPI& epi) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -166,7 +168,7 @@ __device__ __forceinline__ void sell_rows(const Csr& A, const XF& xf, EPI& epi) 
   const int s1 = (int)((long)A.nslices * (lb + 1) / B);
   for (int s = s0 + wid; s < s1; s += NWAVES) {
     const int r = s * SELL_C + lane;
-    const T y = sell_row<T>(A, xf, s, r, lane);
+    const T y = sell_row<T, WIDE>(A, xf, s, r, lane);
     if (r < A.n) epi(r, y);
   }
 }
@@ -529,7 +531,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_proj(Csr A, const T* __restrict_
 // and stages them in LDS, then the block projects the stage's rows as above
 // (wave w: columns w, w + NW, ...).  Eight waves per block double the loads in
 // flight per CU at the same number of blocks, and so of partial sums.
-template <typename T, typename S, int SLOTS, bool SCALED, int NW>
+template <typename T, typename S, int SLOTS, bool SCALED, int NW, bool WIDE>
 __global__ __launch_bounds__(NW * WAVE) void k_spmv_proj_sell(Csr A, const T* __restrict__ src, S* __restrict__ V,
                                                           long ldv, int j, T* __restrict__ w_out, State st,
                                                           T* __restrict__ part, const T* __restrict__ norm_part,
@@ -560,8 +562,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_spmv_proj_sell(Csr A, const T* __
       const int r = sl * SELL_C + lane;
       T y = T(0), vj = T(0);
       if (sl < A.nslices) {
-        if (SCALED) y = sell_row<T>(A, xs, sl, r, lane);
-        else y = sell_row<T>(A, XPlain<T>{src}, sl, r, lane);
+        if (SCALED) y = sell_row<T, WIDE>(A, xs, sl, r, lane);
+        else y = sell_row<T, WIDE>(A, XPlain<T>{src}, sl, r, lane);
         if (r < A.n) {
           w_out[r] = y;
           if (SCALED) {
@@ -1607,12 +1609,12 @@ struct PlainEpi {
   __device__ __forceinline__ void operator()(int r, T v) { y[r] = v; }
 };
 
-template <typename T>
+template <typename T, bool WIDE>
 __global__ __launch_bounds__(BLOCK) void k_spmv(Csr A, const T* __restrict__ x, T* __restrict__ y) {
   T* prod = dyn_lds<T>();  // one entry per nonzero of the largest tile
   __shared__ T s_scr[NWAVES * WAVE];
   PlainEpi<T> epi{y};
-  if (A.sell) sell_rows<T>(A, XPlain<T>{x}, epi);
+  if (A.sell) sell_rows<T, WIDE>(A, XPlain<T>{x}, epi);
   else spmv_tiles<T>(A, XPlain<T>{x}, epi, prod, s_scr);
 }
 

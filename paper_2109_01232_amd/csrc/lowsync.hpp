@@ -132,7 +132,7 @@ __device__ __forceinline__ void ls_store_partials(int C, bool has_p, T alpha, T 
 // cycle start, and v_0 is stored as basis column 0; own[r] is then v_0[r].
 // Otherwise the gather reads gsrc (q_j, or M^{-1} q_j with a preconditioner)
 // and the own-row value comes from own (q_j, or v_0 at iteration 0).
-template <typename T, typename S, int SLOTS, bool SCALED, int NW>
+template <typename T, typename S, int SLOTS, bool SCALED, int NW, bool WIDE>
 __global__ __launch_bounds__(NW * WAVE) void k_ls_spmv_dots_sell(Csr A, const T* __restrict__ gsrc,
                                                               const T* __restrict__ own, S* __restrict__ V, long ldv,
                                                               int j, T* __restrict__ p_out, State st,
@@ -164,8 +164,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_ls_spmv_dots_sell(Csr A, const T*
       const int r = sl * SELL_C + lane;
       T y = T(0), qv = T(0);
       if (sl < A.nslices) {
-        if (SCALED) y = sell_row<T>(A, xs, sl, r, lane);
-        else y = sell_row<T>(A, XPlain<T>{gsrc}, sl, r, lane);
+        if (SCALED) y = sell_row<T, WIDE>(A, xs, sl, r, lane);
+        else y = sell_row<T, WIDE>(A, XPlain<T>{gsrc}, sl, r, lane);
         if (r < A.n) {
           p_out[r] = y;
           if (SCALED) {
