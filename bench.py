@@ -171,7 +171,12 @@ def main():
     log("building the 27-point 128^3 system")
     system = P.varcoef27_system(args.seed)
     A = system.A
+    # matrix set-up (CSR upload, fp32 copy, sliced copy): reported, not in the solve times
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     M = B.Matrix.from_csr(A)
+    torch.cuda.synchronize()
+    t_matrix = time.perf_counter() - t0
     b = torch.from_numpy(system.b).cuda()
     x = torch.zeros_like(b)
     ws = B.Workspace()
@@ -249,6 +254,8 @@ def main():
         "converged": head["converged"],
         "rel_resid_true": head["rel_resid_true"],
         "sol_err_vs_u": head["sol_err_vs_u"],
+        "matrix_setup_s": t_matrix,
+        "matrix_layout": M.layout,
     }
     if "bf16" in results:
         out["bf16_basis"] = results["bf16"]
@@ -575,6 +582,12 @@ def suite(args):
         # the 2D system at its other seeds (Peclet number drawn per seed)
         cases.append((f"convdiff2d_1000_seed{seed}", lambda seed=seed: P.convdiff2d_system(seed),
                       [c("fp64", "fp64", 50), c("fp32", "fp32", 50)]))
+    for seed in (1, 2):
+        # the 3D systems at their other seeds (the 27-point coefficients and u, or u alone, per seed)
+        cases.append((f"varcoef27_128_seed{seed}", lambda seed=seed: P.varcoef27_system(seed),
+                      [c("fp64", "fp64", 50), c("fp32", "fp32", 50), c("fp32", "bf16", 50)]))
+        cases.append((f"aniso3d_150_7pt_seed{seed}", lambda seed=seed: P.aniso3d_system(seed),
+                      [c("fp64", "fp64", 100), c("fp32", "fp32", 100), c("fp32", "fp32", 100, 10)]))
     cases.append(("convdiff2d_64_parity", P.parity_system,
                   [c("fp64", "fp64", 50), c("fp32", "fp32", 50), c("fp32", "bf16", 50)]))
 
@@ -588,7 +601,12 @@ def suite(args):
             continue
         log("suite", name)
         sysm = make_system()
+        # set-up of the matrix (CSR upload, fp32 copy, sliced copy): timed, reported, not in the solve times
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         M = B.Matrix.from_csr(sysm.A)
+        torch.cuda.synchronize()
+        t_matrix = time.perf_counter() - t0
         b = torch.from_numpy(np.asarray(sysm.b, dtype=np.float64)).cuda()
         Asp = sysm.A.scipy()
         bnorm = float(np.linalg.norm(sysm.b))
@@ -630,6 +648,7 @@ def suite(args):
                    "meta": {k: v for k, v in sysm.meta.items() if isinstance(v, (int, float, str))},
                    "inner": inner, "basis": basis, "restart": m, "poly_degree": deg, **extra,
                    "status": B.status_string(st), "time_to_1e-10_s": t, "poly_setup_s": t_setup,
+                   "matrix_setup_s": t_matrix, "layout": M.layout,
                    "iters": d["iters"], "refinements": d["refinements"], "rel_resid_true": true,
                    "converged": bool(true <= 1e-10),
                    "sol_err_vs_u": (rel_err(xs, sysm.u) if sysm.u is not None else None),

@@ -159,6 +159,50 @@ def test_spmv_parity(case):
             assert np.array_equal(y, ref), (prec, np.abs(y - ref).max())
 
 
+def holed_stencil_matrix(side=20, seed=5):
+    """The 7-point Laplacian on side^3 with about 3 % of its off-diagonal
+    entries removed at random, a few explicit zeros kept as entries, and three
+    empty rows (one of them the last row): the rows of a slice then hold
+    different subsets of the slice's offsets, so the shared-offset layout
+    stores zeros in the middle of rows, and a slice has a row with no entry."""
+    A0 = P.stencil_matrix("laplace3d_7", side)
+    S = A0.scipy().tocoo()
+    rng = np.random.default_rng(seed)
+    keep = (S.row == S.col) | (rng.uniform(size=S.nnz) > 0.03)
+    r, c, v = S.row[keep], S.col[keep], S.data[keep].copy()
+    v[rng.choice(len(v), 20, replace=False)] = 0.0  # explicit zeros
+    empty = np.array([5, 777, A0.n - 1])
+    keep = ~np.isin(r, empty)
+    import scipy.sparse as sp
+    H = sp.csr_matrix((v[keep], (r[keep], c[keep])), shape=(A0.n, A0.n))
+    H.sort_indices()
+    return P.CSR(A0.n, H.indptr.astype(np.int32), H.indices.astype(np.int32), H.data)
+
+
+def test_spmv_shared_layout_with_holes():
+    """Shared-offset layout on rows that miss some of their slice's offsets,
+    explicit zeros and empty rows: bitwise the CSR row sums, both precisions
+    (including x with exact zeros and negative zeros)."""
+    A = holed_stencil_matrix()
+    assert A.nnz < P.stencil_nnz("laplace3d_7", 20)
+    M = B.Matrix.from_csr(A)
+    assert M.layout == 3
+    say("spmv shared layout with holes")
+    x = np.random.default_rng(2).uniform(-1, 1, A.n)
+    x[::11] = 0.0
+    x[3::13] = -0.0
+    for prec, dt in (("fp64", np.float64), ("fp32", np.float32)):
+        xd = dev_tensor(x.astype(dt))
+        yd = torch.empty_like(xd)
+        B.gmresir_spmv(M, xd, yd, prec)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy()
+        ref = L.spmv(L.csr_matrix(A, dt), x.astype(dt))
+        assert np.array_equal(y, ref), (prec, np.abs(y - ref).max())
+        assert np.all(y[[5, 777, A.n - 1]] == 0)
+    M.close()
+
+
 # ---------------------------------------------------------------------------
 # full solves on the parity system (64x64 convection-diffusion)
 # ---------------------------------------------------------------------------
