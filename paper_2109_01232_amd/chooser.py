@@ -10,11 +10,11 @@ chooser learns that mapping from solver sweeps the method itself generates.
 Pipeline (every numerical step runs in the library's HIP kernels):
 
 * ``gmresir_features``: 16 fp32 features of (A, b).
-* ``sweep``: per system, the default (m = 50, cap = m, degree 0), six fixed
-  anchor configurations and a few random grid points, each timed end to end
-  (polynomial set-up included) with an iteration budget of twice the
-  incumbent's time; the label is the fastest configuration reaching the fp64
-  residual target.
+* ``sweep``: per system, the default (m = 50, cap = m, degree 0) and 16
+  grid points drawn at random, each timed end to end (polynomial set-up
+  included) and cut off at twice the incumbent's time (an iteration budget
+  from the per-iteration byte model); the label is the fastest configuration
+  reaching the fp64 residual target.
 * ``train``: Adam on the mean squared error of the encoded label
   (log2 m, log2(cap/m), degree/40) with ``gmresir_mlp_train_step``.
 * ``choose``: features -> ``gmresir_mlp_forward`` -> snap to the grid.
@@ -42,8 +42,6 @@ M_GRID = (10, 20, 30, 50, 75, 100, 150, 200)
 CAP_GRID = (1, 2, 4)
 DEG_GRID = (0, 5, 10, 20, 30, 40)
 DEFAULT = (50, 1, 0)
-# configurations tried on every system besides the default (the random draws add coverage)
-ANCHORS = ((30, 1, 0), (100, 1, 0), (50, 1, 10), (100, 1, 20), (30, 1, 20), (50, 4, 0))
 RTOL = 1e-10
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "chooser_weights.json")
 
@@ -119,9 +117,9 @@ def sweep_system(seed: int, n_random: int, rng: np.random.Generator, n_max: floa
     best = base if base["ok"] else None
     t_it = base["time"] / max(base["iters"], 1)
     cost0 = _iter_cost(DEFAULT, sysm.A.n, sysm.A.nnz)
-    cands = [c for c in grid() if c != DEFAULT and c not in ANCHORS]
+    cands = [c for c in grid() if c != DEFAULT]
     idx = rng.choice(len(cands), size=min(n_random, len(cands)), replace=False)
-    for cfg in list(ANCHORS) + [cands[i] for i in idx]:
+    for cfg in [cands[i] for i in idx]:
         budget_t = 2.0 * (best["time"] if best else base["time"] * 4)
         per_it = t_it * _iter_cost(cfg, sysm.A.n, sysm.A.nnz) / cost0
         r = R.run(cfg, max_iters=max(10, int(budget_t / per_it)))
@@ -291,7 +289,7 @@ def main(argv=None):
     s = sub.add_parser("sweep")
     s.add_argument("--start", type=int, required=True)
     s.add_argument("--stop", type=int, required=True)
-    s.add_argument("--n-random", type=int, default=4)
+    s.add_argument("--n-random", type=int, default=16)
     s.add_argument("--n-max", type=float, default=2e6)
     s.add_argument("--rng-seed", type=int, default=2024)
     s.add_argument("--out", required=True)

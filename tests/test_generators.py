@@ -83,6 +83,20 @@ def test_varcoef27_is_m_matrix_with_row_sum():
     assert off.data.min() >= -1.8 - 1e-12 and off.data.max() <= -0.2 + 1e-12
 
 
+def test_varcoef27_shift_and_chooser_families():
+    # the row-sum shift is a parameter; the off-diagonal draws do not depend on it
+    A1, A2 = P.varcoef27(5, 3, shift=0.3), P.varcoef27(5, 3)
+    assert np.max(np.abs(A1.scipy() @ np.ones(A1.n) - 0.3)) <= 1e-13
+    off = A1.colidx != np.repeat(np.arange(A1.n), np.diff(A1.rowptr))
+    assert np.array_equal(A1.vals[off], A2.vals[off])
+    # the chooser population: about a quarter 27-point systems, the rest convection-diffusion
+    fams = [P.chooser_system(s, n_max=2e4).meta["family"] for s in range(400)]
+    k = fams.count("varcoef27")
+    assert 70 <= k <= 130 and fams.count("convdiff") == 400 - k
+    s27 = next(P.chooser_system(s, n_max=2e4) for s in range(400) if fams[s] == "varcoef27")
+    assert 1e-2 <= s27.meta["shift"] <= 1.0 and s27.A.nnz > 20 * s27.A.n
+
+
 def test_seeded_reproducible():
     a = P.convdiff2d_system(3, n=30)
     b = P.convdiff2d_system(3, n=30)
