@@ -299,12 +299,13 @@ def main():
         tt, bb, nl = d_prof["cat_time_s"][dom], d_prof["cat_bytes"][dom], d_prof["cat_launches"][dom]
         achieved = bb / tt / 1e9 if tt > 0 else 0.0
         copy_gbps = device_copy_rate()
+        triad_gbps = device_triad_rate()
         traffic = measured_traffic(dom) if (args.seed == 0 and m == 50 and pv == "fp32") else None
         out["roofline"] = {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom, "variant": pv,
             "avg_launch_us": tt / max(nl, 1) * 1e6, "avg_bytes_per_launch": bb / max(nl, 1),
-            "launches": nl, "measured_copy_GBps": copy_gbps,
+            "launches": nl, "measured_copy_GBps": copy_gbps, "measured_triad_GBps": triad_gbps,
             "bytes_model": "SpMV (4 + 4) nnz + 4 (N + 1) + 2*4 N (x read, w written; 4-byte column indices) + "
                            "4 N per basis column read or written (first CGS2 projection fused)",
         }
@@ -371,6 +372,27 @@ def device_copy_rate():
     e1.record()
     torch.cuda.synchronize()
     return 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def device_triad_rate():
+    """STREAM triad a = b + s c over three 512 MiB fp32 arrays (past the 256 MB
+    Infinity Cache) on the same GPU: bytes read and written per second."""
+    import torch
+
+    b = torch.empty(128 << 20, dtype=torch.float32, device="cuda").uniform_()
+    c = torch.empty_like(b).uniform_()
+    a = torch.empty_like(b)
+    torch.add(b, c, alpha=0.5, out=a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        torch.add(b, c, alpha=0.5, out=a)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = 10 * 3 * b.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b, c
+    torch.cuda.empty_cache()
+    return rate
 
 
 def learned_variant(M, b, x, ws, system, Asp, steps):

@@ -220,7 +220,10 @@ Layout make_layout(int64_t n, const gmresir_params* p) {
   L.u = L.multi ? take(vecT) : 0;
   L.z = need_uz ? take(vecT) : 0;
   L.py = (L.poly || L.bj > 0) ? take(vecT) : 0;
-  L.minv = L.bj > 0 ? take((size_t)((n + L.bj - 1) / L.bj) * L.bj * L.bj * L.sT) : 0;
+  // block-Jacobi inverses by wave group (G = 64 / bs blocks) and column: G * bs entries per column
+  L.minv = L.bj > 0 ? take((size_t)((((n + L.bj - 1) / L.bj) + WAVE / L.bj - 1) / (WAVE / L.bj)) * L.bj *
+                           (WAVE / L.bj * L.bj) * L.sT)
+                    : 0;
   L.p0 = L.poly ? take(vecT) : 0;
   L.p1 = L.poly ? take(vecT) : 0;
   L.p2 = L.poly ? take(vecT) : 0;

@@ -1405,10 +1405,14 @@ constexpr int BJ_MAX = 64;
 // fp32 the round-to-nearest-even copy) into LDS next to an identity (C =
 // double: 66 KB of LDS, gfx950 gives a workgroup up to 160 KB), reduced by
 // Gauss-Jordan elimination with partial pivoting in C, and its inverse
-// written column-major with leading dimension bs: Minv[blk][c][i] =
-// inv(A_bb)[i][c].  The bs pivot steps run in lock step for all blocks of the
-// wave (a ragged last block skips the steps beyond its size).  A zero or
-// non-finite pivot writes NaN (the solve then reports NUMERIC).
+// written by wave group and column: Minv[grp][c][lane] = inv(A_bb)[i][c]
+// (grp = this block's index, lane = g * bs + i < W = G * bs, column stride
+// W), so that for each column the lanes of the applying wave read one
+// contiguous row of W entries (columns past a ragged block's size are never
+// read).  The bs
+// pivot steps run in lock step for all blocks of the wave (a ragged last
+// block skips the steps beyond its size).  A zero or non-finite pivot writes
+// NaN (the solve then reports NUMERIC).
 template <typename C>
 __global__ __launch_bounds__(WAVE) void k_bj_invert(int n, const int* __restrict__ rowptr,
                                                     const int* __restrict__ col, const C* __restrict__ vals,
@@ -1469,15 +1473,20 @@ __global__ __launch_bounds__(WAVE) void k_bj_invert(int n, const int* __restrict
   }
   const C nan = (C)__builtin_nan("");
   if (i < m) {
-    C* out = Minv + (size_t)blk * bs * bs;
-    for (int c = 0; c < m; ++c) out[(size_t)c * bs + i] = bad ? nan : a[lane][m + c];
+    const int W = G * bs;
+    C* out = Minv + (size_t)blockIdx.x * bs * W + lane;
+    for (int c = 0; c < m; ++c) out[(size_t)c * W] = bad ? nan : a[lane][m + c];
   }
 }
 
 // y = M^{-1} x.  A wave takes G = 64 / bs consecutive diagonal blocks at
 // once (lane = g * bs + i: row i of block g; for bs = 8 all 64 lanes work),
 // stages their x in LDS and each lane sums its row of the inverse over the
-// block's columns in ascending order (column reads of a block are contiguous).
+// block's columns in ascending order; the inverses are stored by wave group
+// and column (stride W = G * bs), so each column step is one contiguous load
+// of W entries for the wave (stored block by block, bs = 8 took 8 cache lines
+// per load: 11.4 us per application on the 1000^2 system; a stride of 64 for
+// bs = 42 left 22 of every 64 entries unused, 37.6 -> 52.0 us).
 // SCALED: x is the next basis vector v_j = round(wtmp * inv), which is also
 // stored as basis column j (the fused start of an iteration, as in the
 // polynomial path).  check_done as in the other iteration kernels.
@@ -1513,10 +1522,11 @@ __global__ __launch_bounds__(BLOCK) void k_bj_apply(int n, int bs, const T* __re
     s_x[wid][lane] = xv;
     __builtin_amdgcn_wave_barrier();
     if (i < m) {
-      const T* Mb = Minv + (size_t)blk * bs * bs;
+      const int W = G * bs;
+      const T* Mg = Minv + (size_t)grp * bs * W + lane;
       const T* xs = &s_x[wid][g * bs];
       T acc = T(0);
-      for (int c = 0; c < m; ++c) acc += Mb[(size_t)c * bs + i] * xs[c];
+      for (int c = 0; c < m; ++c) acc += Mg[(size_t)c * W] * xs[c];
       y[r0 + i] = acc;
     }
     __builtin_amdgcn_wave_barrier();

@@ -6,7 +6,8 @@ application kernel (groups of G blocks per wave, grid-stride over groups),
 with the launch grids the host code computes, and checks that every access
 stays inside its buffer: the CSR rows, the LDS tile (64 rows x 129 columns),
 the LDS staging of x (64 entries per wave), the inverse storage the
-workspace reserves (one bs x bs matrix per block) and the vectors (n rows),
+workspace reserves (per wave group of G = 64 / bs blocks, bs columns of
+G bs entries: Minv[grp][c][lane]) and the vectors (n rows),
 for block sizes 1, 24, 42 and 64 (and 8, 64 / bs not integral for 24 and 42)
 with ragged last blocks."""
 import numpy as np
@@ -19,7 +20,7 @@ def invert_accesses(n, bs):
     nblk = -(-n // bs)
     G = WAVE // bs
     grid = -(-nblk // G)  # host: (nblk + per_wave - 1) / per_wave
-    minv_size = nblk * bs * bs
+    minv_size = grid * bs * G * bs  # workspace: ngrp * bs * (G bs) entries
     seen_rows = np.zeros(n, bool)
     seen_minv = np.zeros(minv_size, bool)
     for bid in range(grid):
@@ -39,7 +40,7 @@ def invert_accesses(n, bs):
                 assert base + m - 1 < WAVE
                 assert 2 * m <= 2 * BJ_MAX < 2 * BJ_MAX + 1
                 for c in range(m):
-                    idx = blk * bs * bs + c * bs + i
+                    idx = (bid * bs + c) * (G * bs) + lane
                     assert 0 <= idx < minv_size
                     assert not seen_minv[idx]
                     seen_minv[idx] = True
@@ -49,14 +50,15 @@ def invert_accesses(n, bs):
     # every stored entry of every (possibly ragged) block is written once
     expected = sum(min(bs, n - b * bs) ** 2 for b in range(nblk))
     assert seen_minv.sum() == expected
+    return seen_minv
 
 
-def apply_accesses(n, bs, max_grid=1 << 20):
+def apply_accesses(n, bs, max_grid=1 << 20, written=None):
     nblk = -(-n // bs)
     G = WAVE // bs
     ngrp = -(-nblk // G)
     grid = min(-(-ngrp // NWAVES), max_grid)
-    minv_size = nblk * bs * bs
+    minv_size = ngrp * bs * G * bs
     seen = np.zeros(n, bool)
     for b in range(grid):
         for wid in range(NWAVES):
@@ -74,7 +76,10 @@ def apply_accesses(n, bs, max_grid=1 << 20):
                         seen[r0 + i] = True
                         for c in range(m):
                             assert 0 <= g * bs + c < WAVE  # staged x of the wave
-                            assert 0 <= blk * bs * bs + c * bs + i < minv_size
+                            idx = (grp * bs + c) * (G * bs) + lane
+                            assert 0 <= idx < minv_size
+                            # every inverse entry read was written by the inversion
+                            assert written is None or written[idx]
                 grp += grid * NWAVES
     assert seen.all()
 
@@ -82,8 +87,8 @@ def apply_accesses(n, bs, max_grid=1 << 20):
 @pytest.mark.parametrize("bs", [1, 8, 24, 42, 64])
 @pytest.mark.parametrize("n", [4096, 4113, 1000, 65, 7])
 def test_block_jacobi_index_bounds(n, bs):
-    invert_accesses(n, bs)
-    apply_accesses(n, bs)
+    written = invert_accesses(n, bs)
+    apply_accesses(n, bs, written=written)
 
 
 def test_apply_grid_stride_with_a_capped_grid():
