@@ -33,13 +33,13 @@ def _gpu():
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def conv64():
     s = P.parity_system()
     return s, B.Matrix.from_csr(s.A)
 
 
-def test_switch_zero_is_fp64_gmres(cfg1):
-    s, M = cfg1
+def test_switch_zero_is_fp64_gmres(conv64):
+    s, M = conv64
     say("fd switch 0 vs fp64 solve")
     b = dev_tensor(s.b)
     x0, d0, h0 = B.solve(M, b, restart=50, inner="fp64", rtol=1e-10, check_mode=1, hist_cap=5000)
@@ -50,9 +50,9 @@ def test_switch_zero_is_fp64_gmres(cfg1):
     assert np.array_equal(h0, h1)
 
 
-def test_fd_matches_oracle(cfg1):
-    s, M = cfg1
-    say("fd switch 100 cfg1 vs oracle")
+def test_fd_matches_oracle(conv64):
+    s, M = conv64
+    say("fd switch 100 conv64 vs oracle")
     b = dev_tensor(s.b)
     x, d, h = B.solve_fd(M, b, 100, restart=50, rtol=1e-12, check_mode=0, hist_cap=100000)
     ref = L.gmres_fd(s.A, s.b, 100, m=50, rtol=1e-12, check_mode=0)
@@ -71,11 +71,11 @@ def test_fd_matches_oracle(cfg1):
 
 
 @pytest.mark.parametrize("switch", [50, 120])
-def test_iterate_at_switch(cfg1, switch):
+def test_iterate_at_switch(conv64, switch):
     """max_iters = switch stops after the fp32 phase: its explicit residual
     agrees with the oracle's, and the phase equals one refinement of the
     fp32 GMRES-IR path with inner_cap = switch (same kernels, same bits)."""
-    s, M = cfg1
+    s, M = conv64
     say("fd iterate at switch", switch)
     b = dev_tensor(s.b)
     x, d, h = B.solve_fd(M, b, switch, restart=50, rtol=1e-10, max_iters=switch, hist_cap=1000)
@@ -91,9 +91,9 @@ def test_iterate_at_switch(cfg1, switch):
     assert np.array_equal(h, h2)
 
 
-def test_bf16_basis_phase(cfg1):
-    s, M = cfg1
-    say("fd bf16 basis cfg1")
+def test_bf16_basis_phase(conv64):
+    s, M = conv64
+    say("fd bf16 basis conv64")
     b = dev_tensor(s.b)
     x, d, _ = B.solve_fd(M, b, 100, restart=50, basis="bf16", rtol=1e-10, check_mode=1)
     xs = x.cpu().numpy()
@@ -101,8 +101,8 @@ def test_bf16_basis_phase(cfg1):
     assert np.linalg.norm(s.b - s.A.scipy() @ xs) / np.linalg.norm(s.b) <= 1e-10
 
 
-def test_argument_errors(cfg1):
-    s, M = cfg1
+def test_argument_errors(conv64):
+    s, M = conv64
     say("fd argument errors")
     lib = B.lib()
     for kw, sw in ((dict(inner_cap=100), 50), (dict(poly_degree=5), 50), ({}, -1)):

@@ -29,9 +29,9 @@ def _gpu():
     B.lib()
 
 
-@pytest.mark.parametrize("case", ["cfg1", "aniso3d", "varcoef27", "chooser", "cyclic"])
+@pytest.mark.parametrize("case", ["conv64", "aniso3d", "varcoef27", "chooser", "cyclic"])
 def test_features_match_oracle(case):
-    if case == "cfg1":
+    if case == "conv64":
         s = P.parity_system()
         A, b = s.A, s.b
     elif case == "aniso3d":

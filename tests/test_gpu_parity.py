@@ -42,7 +42,7 @@ def _gpu():
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def conv64():
     s = P.parity_system()
     return s, B.Matrix.from_csr(s.A)
 
@@ -112,15 +112,15 @@ def far_column_matrix(side=264, seed=2, far=True):
 # layout the library picks: 3 = sliced copy with one column-offset list per
 # slice (stencils), 2 = with 16-bit column offsets per entry, 1 = with 32-bit
 # columns, 0 = CSR row tiles only (a row longer than 512)
-SPMV_LAYOUT = {"cfg1": 3, "ragged2d": 3, "aniso3d": 3, "varcoef27": 3, "irregular": 0, "longrow": 0, "farcols": 1,
+SPMV_LAYOUT = {"conv64": 3, "ragged2d": 3, "aniso3d": 3, "varcoef27": 3, "irregular": 0, "longrow": 0, "farcols": 1,
                "nearcols": 2}
 
 
-@pytest.mark.parametrize("case", ["cfg1", "ragged2d", "aniso3d", "varcoef27", "irregular", "longrow", "farcols",
+@pytest.mark.parametrize("case", ["conv64", "ragged2d", "aniso3d", "varcoef27", "irregular", "longrow", "farcols",
                                   "nearcols"])
 def test_spmv_parity(case):
     say("spmv", case)
-    if case == "cfg1":
+    if case == "conv64":
         A = P.parity_system().A
     elif case == "ragged2d":
         A = P.conv_diff(2, 37, 25.0, (1.0, -0.5))
@@ -207,9 +207,9 @@ def test_spmv_shared_layout_with_holes():
 # full solves on the parity system (64x64 convection-diffusion)
 # ---------------------------------------------------------------------------
 
-def test_fp64_gmres_matches_oracle(cfg1):
-    s, M = cfg1
-    say("fp64 gmres(50) cfg1")
+def test_fp64_gmres_matches_oracle(conv64):
+    s, M = conv64
+    say("fp64 gmres(50) conv64")
     b = dev_tensor(s.b)
     x, d, h = B.solve(M, b, restart=50, inner="fp64", rtol=1e-10, check_mode=0, hist_cap=100000)
     ref = L.gmres(s.A, s.b, m=50, rtol=1e-10, check_mode=0)
@@ -227,9 +227,9 @@ def test_fp64_gmres_matches_oracle(cfg1):
     assert np.max(np.abs(h - href)) <= 1e-5
 
 
-def test_gmres_ir_fp32_matches_oracle(cfg1):
-    s, M = cfg1
-    say("ir fp32 cfg1")
+def test_gmres_ir_fp32_matches_oracle(conv64):
+    s, M = conv64
+    say("ir fp32 conv64")
     b = dev_tensor(s.b)
     x, d, h = B.solve(M, b, restart=50, inner="fp32", rtol=1e-12, check_mode=0, hist_cap=100000)
     ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-12, inner="fp32", check_mode=0)
@@ -243,12 +243,12 @@ def test_gmres_ir_fp32_matches_oracle(cfg1):
     assert np.max(np.abs(h[:50] - np.array(ref.hist[:50]))) <= HIST_TOL_FP32
 
 
-def test_ir_cycle_histories_from_oracle_iterates(cfg1):
+def test_ir_cycle_histories_from_oracle_iterates(conv64):
     """Per-cycle parity on the same input r_i: the GPU restarts from the
     oracle's own iterate x_i and runs one fp32 cycle; its history is compared
     with the fp64 oracle's cycle i+1 (the gate oracle runs the inner solve in
     fp64)."""
-    s, M = cfg1
+    s, M = conv64
     ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-12, inner="fp64", check_mode=0, keep_iterates=True)
     cycles = cycle_slices(ref.hist, ref.cycle_starts)
     b = dev_tensor(s.b)
@@ -261,8 +261,8 @@ def test_ir_cycle_histories_from_oracle_iterates(cfg1):
         assert np.max(np.abs(h - cycles[i + 1])) <= HIST_TOL_FP32, i
 
 
-def test_check_mode_implicit_exit(cfg1):
-    s, M = cfg1
+def test_check_mode_implicit_exit(conv64):
+    s, M = conv64
     say("check_mode 1")
     b = dev_tensor(s.b)
     x0, d0, _ = B.solve(M, b, restart=50, inner="fp32", rtol=1e-10, check_mode=0)
@@ -273,9 +273,9 @@ def test_check_mode_implicit_exit(cfg1):
     assert abs(d1["iters"] - ref.iters) <= 10
 
 
-def test_bf16_basis(cfg1):
-    s, M = cfg1
-    say("bf16 basis cfg1")
+def test_bf16_basis(conv64):
+    s, M = conv64
+    say("bf16 basis conv64")
     b = dev_tensor(s.b)
     x, d, h = B.solve(M, b, restart=50, inner="fp32", basis="bf16", rtol=1e-10, check_mode=0, hist_cap=100000)
     ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-10, inner="fp32", basis="bf16", check_mode=0)
@@ -286,8 +286,8 @@ def test_bf16_basis(cfg1):
     assert rel(x.cpu().numpy(), s.u) <= 1e-6
 
 
-def test_deterministic(cfg1):
-    s, M = cfg1
+def test_deterministic(conv64):
+    s, M = conv64
     say("determinism")
     b = dev_tensor(s.b)
     xa, da, _ = B.solve(M, b, restart=30, inner="fp32", rtol=1e-10)
@@ -295,13 +295,13 @@ def test_deterministic(cfg1):
     assert torch.equal(xa, xb) and da["iters"] == db["iters"]
 
 
-def test_graph_replay_matches_direct_launches(cfg1):
+def test_graph_replay_matches_direct_launches(conv64):
     """Systems up to 2^18 rows run their cycles as a recorded HIP graph,
     replayed once per refinement with eager kernels (residual, cast, host
     read) in between; profiling switches to direct launches.  Both give the
     same bits on every refinement (fp32 inner, fp64 inner, bf16 basis, a
     multi-cycle inner cap, and two solves in a row)."""
-    s, M = cfg1
+    s, M = conv64
     b = dev_tensor(s.b)
     for kw in (dict(restart=50, inner="fp32"), dict(restart=30, inner="fp64"),
                dict(restart=40, inner="fp32", basis="bf16"), dict(restart=20, inner="fp32", inner_cap=60)):
@@ -315,8 +315,8 @@ def test_graph_replay_matches_direct_launches(cfg1):
         assert np.array_equal(hg, hd)
 
 
-def test_resume_equals_single_call(cfg1):
-    s, M = cfg1
+def test_resume_equals_single_call(conv64):
+    s, M = conv64
     say("resume")
     b = dev_tensor(s.b)
     full, df, _ = B.solve(M, b, restart=30, inner="fp64", rtol=1e-10, check_mode=0)
@@ -327,8 +327,8 @@ def test_resume_equals_single_call(cfg1):
     assert torch.equal(rest, full)
 
 
-def test_inner_cap_multi_cycle(cfg1):
-    s, M = cfg1
+def test_inner_cap_multi_cycle(conv64):
+    s, M = conv64
     say("inner cap 75, m 25")
     b = dev_tensor(s.b)
     x, d, _ = B.solve(M, b, restart=25, inner="fp32", inner_cap=75, rtol=1e-10)
@@ -464,8 +464,8 @@ def test_exact_breakdown_small_system():
 # failure handling (forced from the host)
 # ---------------------------------------------------------------------------
 
-def test_failure_modes(cfg1):
-    s, M = cfg1
+def test_failure_modes(conv64):
+    s, M = conv64
     b = dev_tensor(s.b)
     say("nan rhs")
     bn = s.b.copy()
