@@ -436,7 +436,7 @@ def learned_variant(M, b, x, ws, system, Asp, steps):
 def extras(args, ws, learned=True):
     """One timed solve each (after a warm-up) on the 2D 1000^2 and 3D 150^3
     systems: GMRES-IR fp32 and fp64 GMRES (150^3 also with a degree-10
-    polynomial, set-up excluded; 1000^2 also the learned-parameter variant).
+    polynomial, set-up excluded) and the learned-parameter variant.
     The oracle's whole solves of these systems take minutes, so each result
     carries its error against the manufactured u and against the fp64 GMRES
     solution instead, and sol_err_vs_oracle is null with the reason."""
@@ -478,7 +478,7 @@ def extras(args, ws, learned=True):
                            "sol_err_vs_oracle": None}
             xsol[label] = xs
             log(f"  {label}: {t:.4f} s iters={d['iters']} resid={true:.2e}")
-        if learned and key.startswith("convdiff2d") and os.path.exists(
+        if learned and os.path.exists(
                 os.path.join(ROOT, "paper_2109_01232_amd", "chooser_weights.json")):
             lv = learned_variant(Mx, bx, xx, ws, s, Asp, 1)
             xsol["learned"] = lv.pop("x")
