@@ -179,6 +179,59 @@ def holed_stencil_matrix(side=20, seed=5):
     return P.CSR(A0.n, H.indptr.astype(np.int32), H.indices.astype(np.int32), H.data)
 
 
+def coupled_stencil_matrix(extra_offsets, side=40):
+    """5-point convection-diffusion on side^2 plus, in every 64-row slice,
+    couplings of its rows to columns r + o for the offsets o in
+    extra_offsets, taken in turn row by row (so a slice's offset union grows
+    by len(extra_offsets) while no row gets more than one extra entry)."""
+    import scipy.sparse as sp
+    A0 = P.conv_diff(2, side, 20.0, (1.0, 0.3))
+    n = A0.n
+    r = np.arange(n)
+    o = np.array(extra_offsets)[r % len(extra_offsets)]
+    keep = (r + o >= 0) & (r + o < n)
+    S = A0.scipy() + sp.csr_matrix((np.full(keep.sum(), -1e-3), (r[keep], (r + o)[keep])), shape=(n, n))
+    S = S.tocsr()
+    S.sort_indices()
+    return P.CSR(n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+
+
+@pytest.mark.parametrize("case,layout", [("two_extra", 3), ("three_extra", 2), ("unsorted_row", 2),
+                                         ("repeated_column", 2)])
+def test_spmv_layout_choice(case, layout):
+    """The shared-offset layout is taken only while a slice's offset union
+    stays within 1.25x the slots of the per-row copy and every row's columns
+    strictly increase: 5 + 2 offsets over rows of at most 6 entries (7/6) keep
+    it, 5 + 3 (8/6) do not; a row stored in decreasing column order, or with a
+    column repeated, keeps the per-entry copy (summed in stored order).  The
+    SpMV is bitwise the CSR sums in stored order either way."""
+    if case == "two_extra":
+        A = coupled_stencil_matrix([3, 5])
+    elif case == "three_extra":
+        A = coupled_stencil_matrix([3, 5, 7])
+    else:
+        A = coupled_stencil_matrix([3, 5])
+        lo, hi = A.rowptr[100], A.rowptr[101]
+        cols, vals = A.colidx.copy(), A.vals.copy()
+        if case == "unsorted_row":
+            cols[lo:hi], vals[lo:hi] = cols[lo:hi][::-1].copy(), vals[lo:hi][::-1].copy()
+        else:
+            cols[lo + 1] = cols[lo]  # the row's second entry repeats its first column
+        A = P.CSR(A.n, A.rowptr, cols, vals)
+    M = B.Matrix.from_csr(A)
+    say("spmv layout choice", case, M.layout)
+    assert M.layout == layout
+    x = np.random.default_rng(4).uniform(-1, 1, A.n)
+    for prec, dt in (("fp64", np.float64), ("fp32", np.float32)):
+        xd = dev_tensor(x.astype(dt))
+        yd = torch.empty_like(xd)
+        B.gmresir_spmv(M, xd, yd, prec)
+        torch.cuda.synchronize()
+        ref = L.spmv(L.csr_matrix(A, dt), x.astype(dt))
+        assert np.array_equal(yd.cpu().numpy(), ref), (case, prec)
+    M.close()
+
+
 def test_spmv_shared_layout_with_holes():
     """Shared-offset layout on rows that miss some of their slice's offsets,
     explicit zeros and empty rows: bitwise the CSR row sums, both precisions
