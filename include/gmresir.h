@@ -146,7 +146,7 @@ size_t gmresir_matrix_storage_bytes(int64_t n, int64_t nnz);
    Otherwise its column indices are 16-bit offsets from the row when every
    entry lies within 32767 columns of its row (the SpMV then reads 6 bytes per
    fp32 nonzero instead of 8), else 32-bit indices.  colidx is copied to the
-   host once to build the offset lists.  Errors: INVALID_ARG (null pointer, n < 1, nnz < 0, nnz >= 2^31, rowptr not
+   host (in windows of at most 16 MB) to build the offset lists.  Errors: INVALID_ARG (null pointer, n < 1, nnz < 0, nnz >= 2^31, rowptr not
    monotone or rowptr[n] != nnz), WORKSPACE (storage too small), HIP. */
 int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
                           const double* vals, void* storage, size_t storage_bytes, void* stream,

@@ -1526,19 +1526,30 @@ int gmresir_matrix_create(int64_t n, int64_t nnz, const int32_t* rowptr, const i
   bool shared = false;
   std::vector<int32_t> sptr3, soff;
   if (sell) {
-    std::vector<int32_t> ci(nnz);
-    HIP_TRY(hipMemcpyAsync(ci.data(), colidx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // the column indices come to the host in windows of at most SHARED_SCAN_WINDOW
+    // entries, 16 MB (a slice's entries, <= 64 * SELL_MAX_ROW, always fit one
+    // window; the 27-point 128^3 matrix takes 14 windows)
+    constexpr int64_t SHARED_SCAN_WINDOW = (int64_t)1 << 22;
+    std::vector<int32_t> ci;
+    int64_t w0 = 0, w1 = 0;  // entries [w0, w1) held in ci
     sptr3.assign(ns + 1, 0);
     std::vector<int32_t> U, row, prev, merged;
     bool ok = true;
     for (int64_t sl = 0; sl < ns && ok; ++sl) {
+      const int64_t ra = sl * SELL_C, rb = std::min<int64_t>(n, (sl + 1) * SELL_C);
+      if (rp[rb] > w1) {
+        w0 = rp[ra];
+        w1 = std::min<int64_t>(nnz, std::max<int64_t>(w0 + SHARED_SCAN_WINDOW, rp[rb]));
+        ci.resize(w1 - w0);
+        HIP_TRY(hipMemcpyAsync(ci.data(), colidx + w0, (w1 - w0) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+      }
       U.clear();
       prev.clear();
-      for (int64_t r = sl * SELL_C; r < std::min<int64_t>(n, (sl + 1) * SELL_C) && ok; ++r) {
+      for (int64_t r = ra; r < rb && ok; ++r) {
         row.clear();
         for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
-          const int32_t d = ci[p] - (int32_t)r;
+          const int32_t d = ci[p - w0] - (int32_t)r;
           if (!row.empty() && d <= row.back()) {
             ok = false;
             break;
