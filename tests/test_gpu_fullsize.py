@@ -10,7 +10,8 @@ comparisons are on outputs it computes one at a time:
   cycle-normalised implicit residual history, 1e-5 for fp32 bases and the
   relative bf16 bar of ``gpu_common.bf16_hist_ok`` for bf16-stored bases, as
   for the small systems -- on the 150^3 system also with a degree-10
-  polynomial built from the oracle's roots (GMRES(100));
+  polynomial built from the oracle's roots (GMRES(100)), and with the
+  one-reduction CGS2 on both 3D systems;
 * later cycles: the GPU restarts from the oracle's own fp64 iterates and runs
   one cycle, compared with the oracle's next cycle;
 * the polynomial preconditioner: the product form with the oracle's roots,
@@ -170,6 +171,36 @@ def test_varcoef27_first_cycle_and_solve(vc27, ws, basis):
     assert d["status"] == B.OK
     true, _ = _true_resid(s, x)
     assert true <= 1e-10 and d["rel_resid_true"] == pytest.approx(true, rel=1e-6)
+
+
+def test_varcoef27_one_reduction_first_cycle_and_solve(vc27, ws):
+    """The one-reduction CGS2 variant the benchmark times beside the
+    headline: first cycle against the oracle's one-reduction fp32 cycle, then
+    the whole solve's fp64 residual."""
+    s, M = vc27
+    b = dev_tensor(s.b)
+    say("ir one-reduction m=50 varcoef27 128^3")
+    x, d, h = B.solve(M, b, ws=ws, restart=50, inner="fp32", ortho="dcgs2", rtol=1e-10, check_mode=1,
+                      hist_cap=1 << 16)
+    ref = L.gmres_ir(s.A, s.b, m=50, rtol=1e-10, inner="fp32", ortho="dcgs2", check_mode=0, max_iters=50)
+    assert np.max(np.abs(h[:50] - np.array(ref.hist[:50]))) <= HIST_TOL_FP32
+    assert d["status"] == B.OK
+    true, _ = _true_resid(s, x)
+    assert true <= 1e-10 and d["rel_resid_true"] == pytest.approx(true, rel=1e-6)
+
+
+def test_aniso3d_one_reduction_first_cycle(an3d, ws):
+    """One-reduction CGS2 at the 150^3 configuration (fp32 GMRES(100), every
+    column class up to 100): first cycle on identical input against the
+    oracle's one-reduction fp32 cycle."""
+    s, M = an3d
+    b = dev_tensor(s.b)
+    say("ir one-reduction m=100 first cycle aniso3d 150^3")
+    x, d, h = B.solve(M, b, ws=ws, restart=100, inner="fp32", ortho="dcgs2", rtol=1e-10, check_mode=0,
+                      max_iters=100, hist_cap=100)
+    ref = L.gmres_ir(s.A, s.b, m=100, rtol=1e-10, inner="fp32", ortho="dcgs2", check_mode=0, max_iters=100)
+    assert d["iters"] == ref.iters == 100
+    assert np.max(np.abs(h - np.array(ref.hist))) <= HIST_TOL_FP32
 
 
 def test_aniso3d_spmv(an3d):
