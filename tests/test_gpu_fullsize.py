@@ -173,6 +173,21 @@ def test_varcoef27_first_cycle_and_solve(vc27, ws, basis):
     assert true <= 1e-10 and d["rel_resid_true"] == pytest.approx(true, rel=1e-6)
 
 
+def test_varcoef27_fp64_gmres_first_cycle_and_solve(vc27, ws):
+    """The fp64 GMRES(50) the headline compares against: first cycle against
+    the oracle's fp64 cycle (fp64 on both sides: 1e-10), then the whole
+    solve's fp64 residual."""
+    s, M = vc27
+    b = dev_tensor(s.b)
+    say("fp64 gmres m=50 varcoef27 128^3")
+    x, d, h = B.solve(M, b, ws=ws, restart=50, inner="fp64", rtol=1e-10, check_mode=1, hist_cap=1 << 16)
+    ref = L.gmres(s.A, s.b, m=50, rtol=1e-10, check_mode=0, max_iters=50)
+    assert np.max(np.abs(h[:50] - np.array(ref.hist[:50]))) <= 1e-10
+    assert d["status"] == B.OK
+    true, _ = _true_resid(s, x)
+    assert true <= 1e-10 and d["rel_resid_true"] == pytest.approx(true, rel=1e-6)
+
+
 def test_varcoef27_one_reduction_first_cycle_and_solve(vc27, ws):
     """The one-reduction CGS2 variant the benchmark times beside the
     headline: first cycle against the oracle's one-reduction fp32 cycle, then
