@@ -650,7 +650,8 @@ def suite(args):
                 torch.cuda.synchronize()
                 t_setup = time.perf_counter() - t0
             kw = dict(restart=m, inner=inner, basis=basis, rtol=1e-10, check_mode=1, poly_degree=deg,
-                      poly_prec=extra.get("poly_prec"), bj_block=extra.get("bj", 0), ortho=extra.get("ortho", 0))
+                      poly_prec=extra.get("poly_prec"), bj_block=extra.get("bj", 0), ortho=extra.get("ortho", 0),
+                      max_iters=args.max_iters)
             p = B.make_params(**kw)
             if "fd" in extra:
                 x = torch.zeros_like(b)

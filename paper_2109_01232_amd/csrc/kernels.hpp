@@ -902,9 +902,10 @@ __global__ __launch_bounds__(BLOCK) void k_update(int n, const T* __restrict__ w
 // rotations, by one block of any size (the extra block of
 // k_reduce_h1_givens, or k_norm_givens after a cycle's last step).  The
 // column and the earlier rotations are staged in LDS so the sequential part
-// (thread 0) touches no global memory.
+// (thread 0) touches no global memory.  Returns the flags it set (the same
+// value in every thread).
 template <typename T>
-__device__ __forceinline__ void givens_tail(const State& st, int j, int kmax, T nrm2, T* s_col, T* s_cs, T* s_sn) {
+__device__ __forceinline__ int givens_tail(const State& st, int j, int kmax, T nrm2, T* s_col, T* s_cs, T* s_sn) {
   __shared__ T s_sq[16];
   __shared__ int s_flags;
   __shared__ T s_g[2];
@@ -913,6 +914,9 @@ __device__ __forceinline__ void givens_tail(const State& st, int j, int kmax, T 
   const double* h1 = st.h1_of(j);
   double* Hc = st.Hbar + (size_t)j * ld;
   double* Rc = st.R + (size_t)j * ld;
+  // read before the stores below, which the compiler cannot tell apart from
+  // these fields (written only at a cycle's set-up)
+  const double gin_d = hd->gamma_in, stop_abs = hd->stop_abs;
   T sq = T(0);
   for (int i = threadIdx.x; i <= j; i += blockDim.x) {
     const T v = (T)h1[i] + (T)st.h2[i];
@@ -936,6 +940,8 @@ __device__ __forceinline__ void givens_tail(const State& st, int j, int kmax, T 
       hd->k = j;
     } else {
       T cur = s_col[0];
+      // unrolled so the LDS reads of several rotations are in flight at once
+#pragma unroll 8
       for (int i = 0; i < j; ++i) {
         T nxt = s_col[i + 1];
         const T c = s_cs[i], s = s_sn[i];
@@ -959,13 +965,13 @@ __device__ __forceinline__ void givens_tail(const State& st, int j, int kmax, T 
       const T gj1 = -s * gj;
       st.g[j] = (double)(c * gj);
       st.g[j + 1] = (double)gj1;
-      const T gin = (T)hd->gamma_in;
+      const T gin = (T)gin_d;
       st.hist[j] = (double)(fabs(gj1) / gin);
       hd->k = j + 1;
       hd->implicit = (double)fabs(gj1);
       hd->inv_h = (double)(T(1) / hn);
       const bool breakdown = hn <= (T)(100.0 * Unit<T>::roundoff) * colnorm;
-      const bool stopped = hd->stop_abs >= 0.0 && fabs(gj1) <= (T)hd->stop_abs;
+      const bool stopped = stop_abs >= 0.0 && fabs(gj1) <= (T)stop_abs;
       flags = (breakdown ? F_BREAKDOWN : 0) | (stopped ? F_STOPPED : 0);
       if (breakdown || stopped || j + 1 >= kmax) flags |= F_DONE;
     }
@@ -980,6 +986,7 @@ __device__ __forceinline__ void givens_tail(const State& st, int j, int kmax, T 
     Hc[i] = 0.0;
     Rc[i] = 0.0;
   }
+  return s_flags;
 }
 
 // Each lane owns four consecutive rows (16-byte loads for fp32); the padded

@@ -274,7 +274,6 @@ __global__ __launch_bounds__(BLOCK) void k_ls_dense(State st, const double* __re
   __shared__ T s_cs[MAX_RESTART];
   __shared__ T s_sn[MAX_RESTART];
   __shared__ T s_red[16];
-  __shared__ int s_flags;
   StateHdr* hd = st.hdr;
   if (load_flags(hd) & F_DONE) return;
   if (j == 0) {
@@ -296,39 +295,47 @@ __global__ __launch_bounds__(BLOCK) void k_ls_dense(State st, const double* __re
   }
   aa = block_sum_any(aa, s_red);  // ends with a barrier: s_a and h2 complete
   const T nrm2 = fmax((T)red[LS_ALPHA] - aa, T(0));
-  givens_tail<T>(st, j - 1, kmax, nrm2, s_col, s_cs, s_sn);
-  __syncthreads();
-  if (threadIdx.x == 0) s_flags = hd->flags;  // written by this thread in givens_tail
-  __syncthreads();
-  if (s_flags & F_DONE) return;  // stop, breakdown, NaN, or the cycle's last column
+  const int flags = givens_tail<T>(st, j - 1, kmax, nrm2, s_col, s_cs, s_sn);
+  if (flags & F_DONE) return;  // stop, breakdown, NaN, or the cycle's last column
   const T rho = sqrt(nrm2);
   const int ld = st.ld;
   // H[0:j+1, 0:j] staged in LDS (dynamic, (j + 1) j entries) with coalesced
   // loads of whole columns; a row-by-row walk through global memory made this
-  // block latency bound (j dependent-address loads per thread)
+  // block latency bound (j dependent-address loads per thread).  The loads are
+  // unconditional (a load under a branch is waited for where the branch ends,
+  // which made the batch one round trip per load): past the end a thread
+  // reads entry 0, and every (l, i) with l < j <= m, i <= j lies inside the
+  // (m + 1) x m array; entries below the subdiagonal are discarded after the
+  // load.  The empty asm keeps each load ahead of the branch of its store.
   T* sH = dyn_lds<T>();
   const int hj = j + 1;
   const int tot = hj * j;
-  constexpr int BATCH = 8;  // loads in flight per thread before their LDS stores
+  constexpr int BATCH = 16;  // loads in flight per thread before their LDS stores
   for (int e0 = 0; e0 < tot; e0 += BLOCK * BATCH) {
-    T v[BATCH];
+    double v[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int e = e0 + (int)threadIdx.x + BLOCK * u;
+      const int ec = e < tot ? e : 0;
+      const int l = ec / hj, i = ec - l * hj;
+      v[u] = st.Hbar[(size_t)l * ld + i];
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) asm volatile("" : "+v"(v[u]));
 #pragma unroll
     for (int u = 0; u < BATCH; ++u) {
       const int e = e0 + (int)threadIdx.x + BLOCK * u;
       const int l = e / hj, i = e - l * hj;
-      v[u] = (e < tot && i <= l + 1) ? (T)st.Hbar[(size_t)l * ld + i] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < BATCH; ++u) {
-      const int e = e0 + (int)threadIdx.x + BLOCK * u;
-      if (e < tot) sH[e] = v[u];
+      if (e < tot) sH[e] = i <= l + 1 ? (T)v[u] : T(0);
     }
   }
   __syncthreads();
-  // t = H[0:j+1, 0:j] a (upper Hessenberg: row i starts at column i - 1)
+  // t = H[0:j+1, 0:j] a (upper Hessenberg: row i starts at column i - 1),
+  // unrolled so several LDS reads are in flight
   T ac = T(0);
   for (int i = threadIdx.x; i <= j; i += blockDim.x) {
     T t = T(0);
+#pragma unroll 8
     for (int l = i > 0 ? i - 1 : 0; l < j; ++l) t += sH[l * hj + i] * s_a[l];
     s_t[i] = t;
     if (i < j) {
