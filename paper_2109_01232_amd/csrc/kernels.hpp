@@ -364,6 +364,24 @@ __device__ __forceinline__ T prev_inv_norm(const State& st, const T* norm_part, 
   return T(1) / sqrt(s_n[0]);
 }
 
+// x where keep holds, else +0 (also for NaN x: the padded rows past n are
+// never written), by a bit mask: a select fed by LDS reads is turned into a
+// branch by the compiler, and a branch makes its waits for memory inexact
+__device__ __forceinline__ float zero_unless(float x, bool keep) {
+  return __uint_as_float(__float_as_uint(x) & (keep ? 0xffffffffu : 0u));
+}
+__device__ __forceinline__ double zero_unless(double x, bool keep) {
+  return __longlong_as_double(__double_as_longlong(x) & (keep ? -1ll : 0ll));
+}
+
+// Basis-column loads of the fused projection issued together per row group
+// (one 16-byte load each).  Written as branches, each column's load was
+// waited for before the next one went out; a batch keeps PROJ_BATCH in
+// flight at a moderate register cost (27-point 128^3 SpMV + projection 92.6
+// -> 88.7 us, 150^3 169.3 -> 165.3 us; batches of 8 and 16 measured no better
+// here, having fewer blocks per CU).
+constexpr int PROJ_BATCH = 4;
+
 // w = A v_j and the partial sums of h1 = V_{j+1}^T w.
 //
 // Per tile: the SpMV products are staged in LDS and summed per row (one
@@ -382,16 +400,30 @@ struct ProjGroup;  // rows per lane of the projection: one 16-byte load (fp64: t
 template <>
 struct ProjGroup<float, float> {
   static constexpr int G = 4;
+  using raw = float4;
+  static __device__ __forceinline__ raw load_raw(const float* p) { return *(const float4*)p; }
+  static __device__ __forceinline__ float get(const raw& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
   static __device__ __forceinline__ void load(const float* p, float (&v)[4]) { Quad<float, float>::load(p, v); }
+};
+struct Double4 {
+  double2 lo, hi;
 };
 template <>
 struct ProjGroup<double, double> {
   static constexpr int G = 4;
+  using raw = Double4;
+  static __device__ __forceinline__ raw load_raw(const double* p) { return {*(const double2*)p, *(const double2*)(p + 2)}; }
+  static __device__ __forceinline__ double get(const raw& v, int i) {
+    return i == 0 ? v.lo.x : i == 1 ? v.lo.y : i == 2 ? v.hi.x : v.hi.y;
+  }
   static __device__ __forceinline__ void load(const double* p, double (&v)[4]) { Quad<double, double>::load(p, v); }
 };
 template <>
 struct ProjGroup<bf16_t, float> {
   static constexpr int G = 8;
+  using raw = uint4;
+  static __device__ __forceinline__ raw load_raw(const bf16_t* p) { return *(const uint4*)p; }
+  static __device__ __forceinline__ float get(const raw& v, int i) { return Packed<bf16_t, float, 8>::get(v, i); }
   static __device__ __forceinline__ void load(const bf16_t* p, float (&v)[8]) {
     const uint4 q = *(const uint4*)p;
 #pragma unroll
@@ -402,9 +434,50 @@ struct ProjGroup<bf16_t, float> {
 template <typename T, typename S, int SLOTS, bool SCALED, int NW = NWAVES>
 __device__ __forceinline__ void project_rows(const S* __restrict__ V, long ldv, int j, int C, int base, int nrows,
                                              const T* ys, const T* vs, T (&acc)[SLOTS], int lane, int wid) {
-  constexpr int G = ProjGroup<S, T>::G;
+  using PG = ProjGroup<S, T>;
+  constexpr int G = PG::G;
   const bool aligned = (base % G) == 0;
   const int ngroups = (nrows + G - 1) / G;
+  if (aligned) {
+    // every load unconditional: columns past C, and column j (whose values
+    // come from vs), read column 0 of the same rows, which lie below the
+    // padded length ldv; rows past the batch are masked by bit, since the
+    // padded rows past n are never written
+    constexpr int QB = SLOTS < PROJ_BATCH ? SLOTS : PROJ_BATCH;
+    for (int g = lane; g < ngroups; g += WAVE) {
+      const int rb = g * G;
+      T yv[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) yv[i] = zero_unless(ys[rb + i], rb + i < nrows);
+#pragma unroll
+      for (int q0 = 0; q0 < SLOTS; q0 += QB) {
+        typename PG::raw rv[QB];
+#pragma unroll
+        for (int u = 0; u < QB; ++u) {
+          const int c = wid + NW * (q0 + u);
+          const bool from_v = c < C && !(SCALED && c == j);
+          rv[u] = PG::load_raw(V + (size_t)(from_v ? c : 0) * ldv + base + rb);
+        }
+#pragma unroll
+        for (int u = 0; u < QB; ++u) {
+          const int c = wid + NW * (q0 + u);
+          if (c < C) {
+            T vv[G];
+            if (SCALED && c == j) {
+#pragma unroll
+              for (int i = 0; i < G; ++i) vv[i] = zero_unless(vs[rb + i], rb + i < nrows);
+            } else {
+#pragma unroll
+              for (int i = 0; i < G; ++i) vv[i] = zero_unless(PG::get(rv[u], i), rb + i < nrows);
+            }
+#pragma unroll
+            for (int i = 0; i < G; ++i) acc[q0 + u] += vv[i] * yv[i];
+          }
+        }
+      }
+    }
+    return;
+  }
   for (int g = lane; g < ngroups; g += WAVE) {
     const int rb = g * G;
     const bool full = aligned && rb + G <= nrows;
@@ -671,13 +744,6 @@ __device__ __forceinline__ void store_vec(T* p, const T (&v)[R]) {
   }
 }
 
-// x where keep holds, else +0 (also for NaN x: the padded rows past n are
-// never written), by a bit mask: a select fed by LDS reads is turned into a
-// branch by the compiler, and a branch makes its waits for memory inexact
-__device__ __forceinline__ float zero_unless(float x, bool keep) {
-  return __uint_as_float(__float_as_uint(x) & (keep ? 0xffffffffu : 0u));
-}
-
 // The steps of k_update_proj with the basis loads of step s + 1 issued
 // before the barrier of step s (two register sets used in turn), so they are
 // in flight while the block waits and finishes step s.  Every load is
@@ -809,45 +875,39 @@ __global__ __launch_bounds__(WV * WAVE) void k_update_proj(int n, const T* __res
       T s[R];
       // narrow bases: w's load goes out with V's, before the barrier (with few
       // columns the step is otherwise two dependent memory round trips); wide
-      // ones load it after the barrier to keep registers for V
+      // ones load it after the barrier to keep registers for V.  Lanes past
+      // the block's rows load the step's first row (below n, and loaded by
+      // lane 0 for the same column) instead of branching: a load under a
+      // per-lane branch is waited for where the branch ends, which split a
+      // step's basis loads into two round trips; only the wave-uniform column
+      // test stays a branch (rows past the range are masked where used, w' by
+      // a bit mask).  27-point 128^3: 42.2 -> 39.8 us per launch.
       constexpr bool W_EARLY = SLOTS <= 4;
       T wv[R];
-      if constexpr (W_EARLY) {
-        if (nv > 0) {
-          load_vec<T, R>(w_in + r, wv);
-        } else {
+      if constexpr (W_EARLY) load_vec<T, R>(w_in + (nv > 0 ? r : base), wv);
 #pragma unroll
-          for (int i = 0; i < R; ++i) wv[i] = T(0);
-        }
+      for (int q = 0; q < SLOTS; ++q) {
+        const int c = wid + WV * q;
+        vr[q] = c < k ? P::load(V + (size_t)c * ldv + (nv > 0 ? r : base)) : P::zero();
       }
 #pragma unroll
       for (int i = 0; i < R; ++i) s[i] = T(0);
 #pragma unroll
-      for (int q = 0; q < SLOTS; ++q) {
-        const int c = wid + WV * q;
-        vr[q] = (c < k && nv > 0) ? P::load(V + (size_t)c * ldv + r) : P::zero();
+      for (int q = 0; q < SLOTS; ++q)
 #pragma unroll
         for (int i = 0; i < R; ++i) s[i] += hq[q] * ((i < nv) ? P::get(vr[q], i) : T(0));
-      }
 #pragma unroll
       for (int i = 0; i < R; ++i) s_part[buf][wid][R * lane + i] = s[i];
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < SLOTS; ++q) P::hold(vr[q]);
-      if constexpr (!W_EARLY) {
-        if (nv > 0) {
-          load_vec<T, R>(w_in + r, wv);
-        } else {
-#pragma unroll
-          for (int i = 0; i < R; ++i) wv[i] = T(0);
-        }
-      }
+      if constexpr (!W_EARLY) load_vec<T, R>(w_in + (nv > 0 ? r : base), wv);
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const int e = R * lane + i;
         T t = (s_part[buf][0][e] + s_part[buf][1][e]) + (s_part[buf][2][e] + s_part[buf][3][e]);
         if constexpr (WV == 8) t += (s_part[buf][4][e] + s_part[buf][5][e]) + (s_part[buf][6][e] + s_part[buf][7][e]);
-        wv[i] = (i < nv) ? wv[i] - t : T(0);
+        wv[i] = zero_unless(wv[i] - t, i < nv);
       }
       if (wid == 0 && nv > 0) {
         if (nv >= R) {
