@@ -1072,7 +1072,9 @@ __global__ __launch_bounds__(NT) void k_update_norm(int n, const T* __restrict__
     const int nv = r1 - r < 4 ? r1 - r : 4;
     T wv[4];
     Quad<T, T>::load(w_in + r, wv);
-#pragma unroll 4
+    // 16 columns' loads per unrolled step: 27-point 128^3 36.8 -> 33.8 us per
+    // launch, 150^3 126.6 -> 118.3 us (unrolling by 8 measured slower than 4)
+#pragma unroll 16
     for (int c = 0; c < k; ++c) {
       T v[4];
       Quad<S, T>::load(V + (size_t)c * ldv + r, v);
