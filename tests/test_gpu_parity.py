@@ -449,6 +449,42 @@ def test_ragged_rows_every_basis_width(m, inner, basis):
     assert np.linalg.norm(bb - A.scipy() @ x.cpu().numpy()) / np.linalg.norm(bb) <= 1e-10
 
 
+@pytest.mark.parametrize("m", [20, 64, 100, 128])
+@pytest.mark.parametrize("inner,basis", [("fp64", "fp64"), ("fp32", "fp32"), ("fp32", "bf16")])
+def test_sliced_path_ragged_rows(m, inner, basis):
+    """The fused sliced kernels (shared-offset layout) on n = 259^2 = 67081
+    rows (1049 slices; n = 1 mod 4 and 9 mod 64, so the last row group of
+    the branch-free basis loads straddles n and only the mask keeps the
+    padded rows out): every column-count class, the first cycle against the
+    oracle's, and the whole solve's fp64 residual for the fp32 and fp64
+    bases."""
+    A = P.conv_diff(2, 259, 30.0, (1.0, -0.5))
+    u = np.random.default_rng(m).uniform(-1, 1, A.n)
+    bb = A.scipy() @ u
+    M = B.Matrix.from_csr(A)
+    assert M.layout == 3
+    b = dev_tensor(bb)
+    say("sliced ragged", m, inner, basis)
+    x, d, h = B.solve(M, b, restart=m, inner=inner, basis=basis, rtol=1e-10, check_mode=0, max_iters=m,
+                      hist_cap=m + 8)
+    if inner == "fp64":
+        ref = L.gmres(A, bb, m=m, rtol=1e-10, check_mode=0, max_iters=m)
+        tol = 1e-10
+    else:
+        ref = L.gmres_ir(A, bb, m=m, rtol=1e-10, inner="fp32", basis=basis, check_mode=0, max_iters=m)
+        tol = HIST_TOL_FP32
+    k = min(m, len(ref.hist))
+    if basis == "bf16":
+        ok, info = bf16_hist_ok(h[:k], ref.hist[:k])
+        assert ok, info
+    else:
+        assert np.max(np.abs(h[:k] - np.array(ref.hist[:k]))) <= tol
+        x, d, _ = B.solve(M, b, restart=m, inner=inner, basis=basis, rtol=1e-10, check_mode=1, max_iters=50000)
+        assert d["status"] == B.OK
+        assert np.linalg.norm(bb - A.scipy() @ x.cpu().numpy()) / np.linalg.norm(bb) <= 1e-10
+    M.close()
+
+
 def test_row_tiled_path_solve():
     """A row longer than the sliced-ELLPACK limit (512) keeps the matrix on
     the row-tiled CSR kernels (LDS-staged products, block-reduced long row):
