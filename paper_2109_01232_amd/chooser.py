@@ -256,7 +256,8 @@ def cmd_evaluate(args):
         base = R.run(DEFAULT)
         chooser.choose(R.features())  # warm-up of the feature and network kernels
         r, total, cfg, t_choice = solve_with_chooser(R, chooser)
-        rec = {"seed": seed, "n": sysm.A.n, "default": base, "chosen": list(cfg), "chosen_run": r,
+        rec = {"seed": seed, "n": sysm.A.n, "family": sysm.meta.get("family"), "default": base, "chosen": list(cfg),
+               "chosen_run": r,
                "choice_time": t_choice, "chosen_total": total,
                "speedup": (base["time"] / total) if base["ok"] else None}
         for fixed in args.also:
